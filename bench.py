@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""FCFS rescale benchmark on one MI355X.
+
+One step is one pass of the fused forward over the batched workload
+N=32, C=3, 1024x1024 FP32 (seeded U[0,1) values), at every scale factor
+{3/2, 2/3, 5/4, 4/5}, every method {nearest, bilinear, bicubic} and both
+paddings {zero, reflect}: 24 launches. The reported value is the achieved
+algorithmic HBM throughput of the step (GB/s): for each launch, the input rows
+any tap reads (full rows) plus the output, summed, over the step's time.
+
+Printed as one JSON line, with:
+  roofline     : the kernel instance with the most time in the step, its
+                 algorithmic bytes per launch over its average launch time,
+                 against the 8 TB/s HBM peak (traffic: measured HBM bytes per
+                 launch from rocprofv3 counters when a summary for the current
+                 kernel source is committed under profiles/, else null);
+  cpu_baseline : the FP64 oracle on the host cores over a bounded sample of
+                 the same launches (a few planes of each);
+  breakdown    : per-case times and GB/s, the BF16 sweep beside the FP32 one.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FRACS = [(3, 2), (2, 3), (5, 4), (4, 5)]
+METHODS = ["nearest", "bilinear", "bicubic"]
+PADS = ["zero", "reflect"]
+SHAPE = (32, 3, 1024, 1024)
+
+
+def rows_touched(fc, plan, n_in: int, axis: int) -> int:
+    """Input rows in [0, n_in) that some tap of some output reads (height axis
+    of the isotropic plans benchmarked here)."""
+    p, q, T = plan.p_red, plan.q_red, plan.taps
+    cells = (n_in + q - 1) // q
+    hit = np.zeros(n_in + 64, dtype=bool)
+    base = np.arange(cells) * q
+    for j in range(p):
+        off = fc.fcfs_plan_taps(plan.handle, axis, j)[0]
+        for t in range(T):
+            idx = base + off + t
+            idx = idx[(idx >= 0) & (idx < n_in)]
+            hit[idx] = True
+    return int(hit[:n_in].sum())
+
+
+def case_bytes(fc, plan, shape, esize: int) -> int:
+    n, c, h, w = shape
+    ho, wo = plan.output_size(h, w)
+    return n * c * (rows_touched(fc, plan, h, 0) * w + ho * wo) * esize
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fwd.hip", "api.cpp", "fcfs_internal.h"):
+        with open(os.path.join(ROOT, "paper_2203_10670_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_id: int):
+    path = os.path.join(ROOT, "profiles", "fwd_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    e = d.get("kernels", {}).get(str(kernel_id))
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def cpu_baseline(cases, x_np, target_planes: int):
+    import oracle
+    threads = oracle.threads()
+    k = max(1, min(SHAPE[0] * SHAPE[1], target_planes or 2 * threads))
+    planes = x_np.reshape(-1, SHAPE[2], SHAPE[3])[:k][:, None].astype(np.float64)
+    total_bytes = 0
+    t0 = time.perf_counter()
+    for cs in cases:
+        oracle.forward(planes, cs["p"], cs["q"], cs["method"], cs["pad"])
+        total_bytes += cs["bytes"] * k // (SHAPE[0] * SHAPE[1])
+    dt = time.perf_counter() - t0
+    return {"value": round(total_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": min(threads, k),
+            "kind": "oracle",
+            "sample": "FP64 oracle, %d of %d planes of each of the %d FP32 launches of a step "
+                      "(%.1f s wall)" % (k, SHAPE[0] * SHAPE[1], len(cases), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the rescale path has no multi-GPU mode "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2203_10670_amd as fc
+    import synth
+
+    dev = torch.device("cuda:0")
+    stream_ptr = torch.cuda.current_stream(dev).cuda_stream
+    x_np = synth.uniform(2, SHAPE)
+    x32 = torch.from_numpy(x_np).to(dev)
+    xbf = x32.to(torch.bfloat16)
+
+    def make_cases(dtype_name, xt, esize):
+        cases = []
+        for (p, q) in FRACS:
+            for m in METHODS:
+                for pad in PADS:
+                    pl = fc.Plan(p, q, m, pad)
+                    ho, wo = pl.output_size(SHAPE[2], SHAPE[3])
+                    y = torch.empty((SHAPE[0], SHAPE[1], ho, wo), dtype=xt.dtype, device=dev)
+                    code = fc.DTYPES[dtype_name]
+                    kid = fc.fcfs_forward_config(pl.handle, code, SHAPE[0], SHAPE[1], SHAPE[2], SHAPE[3])[0]
+                    cases.append({"p": p, "q": q, "method": m, "pad": pad, "plan": pl, "y": y, "x": xt,
+                                  "code": code, "kernel_id": kid, "dtype": dtype_name,
+                                  "bytes": case_bytes(fc, pl, SHAPE, esize)})
+        return cases
+
+    def launch(cs):
+        st = fc.fcfs_forward(cs["plan"].handle, cs["code"], SHAPE[0], SHAPE[1], SHAPE[2], SHAPE[3],
+                             cs["x"].data_ptr(), None, SHAPE[1], cs["y"].data_ptr(), stream_ptr)
+        if st != 0:
+            raise fc.FcfsError(st, "fcfs_forward")
+
+    def timed_sweep(cases, steps, warmup):
+        for _ in range(warmup):
+            for cs in cases:
+                launch(cs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            for cs in cases:
+                launch(cs)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def per_case(cases, reps):
+        out = []
+        for cs in cases:
+            launch(cs)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                launch(cs)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1000.0 / reps
+            out.append((cs, us))
+        return out
+
+    f32 = make_cases("f32", x32, 4)
+    ms_step = timed_sweep(f32, args.steps, args.warmup)
+    step_bytes = sum(c["bytes"] for c in f32)
+    value = step_bytes / (ms_step * 1e-3) / 1e9
+    print("step: %.3f ms, %.1f GB/s" % (ms_step, value), file=sys.stderr, flush=True)
+
+    reps = max(3, args.steps)
+    pc = per_case(f32, reps)
+    groups = {}
+    for cs, us in pc:
+        g = groups.setdefault(cs["kernel_id"], {"us": 0.0, "bytes": 0, "n": 0})
+        g["us"] += us
+        g["bytes"] += cs["bytes"]
+        g["n"] += 1
+    dom = max(groups.items(), key=lambda kv: kv[1]["us"])
+    kid, g = dom
+    avg_us = g["us"] / g["n"]
+    bytes_per_launch = g["bytes"] / g["n"]
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kid),
+                "kernel_id": kid, "launches": g["n"], "avg_us": round(avg_us, 2),
+                "bytes_per_launch": int(bytes_per_launch)}
+
+    breakdown = {"f32": [{"case": "%d/%d %s %s" % (c["p"], c["q"], c["method"], c["pad"]),
+                          "us": round(us, 2), "GBps": round(c["bytes"] / (us * 1e-6) / 1e9, 1),
+                          "kernel_id": c["kernel_id"]} for c, us in pc]}
+    bf16_value = None
+    if not args.no_bf16:
+        del pc
+        bf = make_cases("bf16", xbf, 2)
+        ms_bf = timed_sweep(bf, args.steps, args.warmup)
+        bf16_value = sum(c["bytes"] for c in bf) / (ms_bf * 1e-3) / 1e9
+        pcb = per_case(bf, reps)
+        breakdown["bf16"] = [{"case": "%d/%d %s %s" % (c["p"], c["q"], c["method"], c["pad"]),
+                              "us": round(us, 2), "GBps": round(c["bytes"] / (us * 1e-6) / 1e9, 1)}
+                             for c, us in pcb]
+        breakdown["bf16_step_ms"] = round(ms_bf, 4)
+        breakdown["bf16_GBps"] = round(bf16_value, 1)
+        del bf, pcb
+    torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(f32, x_np, args.cpu_planes)
+
+    line = {
+        "metric": "resample output GB/s vs HBM peak (FP32, BF16); served p50/p99 latency",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "FCFS forward sweep: N=32 C=3 1024x1024 FP32 U[0,1); scales 3/2 2/3 5/4 4/5; "
+                               "nearest bilinear bicubic; zero and reflect padding (24 launches per step)",
+                   "batch": SHAPE[0], "channels": SHAPE[1], "height": SHAPE[2], "width": SHAPE[3],
+                   "launches_per_step": len(f32), "bytes_per_step": step_bytes},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "bf16_value": None if bf16_value is None else round(bf16_value, 1),
+        "breakdown": breakdown,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

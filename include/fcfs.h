@@ -1,0 +1,179 @@
+/*
+ * fcfs.h — C ABI of libfcfs, fully convolutional fractional scaling (FCFS)
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * FCFS rescales each channel of an NCHW tensor by a rational factor p/q in
+ * three steps (paper, Sec. 3.1 and its 2D form in Sec. 4.2):
+ *   1. pad the input (Sec. 3, "Padding"),
+ *   2. a stride-q convolution with p*p output channels per input channel, one
+ *      per interpolation phase (Sec. 3, "Stride"; Sec. 3.1.1),
+ *   3. pixelshuffle by p (Sec. 3, "Pixel Shuffling"; Sec. 4.1).
+ * libfcfs fuses the three steps into one kernel: the padding is applied while
+ * loading, the hidden layer is never written, and each output sample is
+ * stored once at its pixelshuffled position.
+ *
+ * Conventions shared by every entry point
+ *  - Tensors are dense, row-major NCHW, element-aligned device pointers owned
+ *    by the caller. Scalars and tables are owned by the library.
+ *  - p/q is reduced by its gcd; the output of an axis of length n has
+ *    p * ceil(n / q) samples (Sec. 3.1.1: the hidden layer has ceil(n/q) cells;
+ *    Sec. 5.1: 5 samples at 3/2 give 9).
+ *  - Output sample k = p*m + j (cell m, phase j) samples the input at
+ *    u = (k + 1/2) q/p - 1/2 (half-pixel grid, the default) — see fcfs_grid.
+ *  - Weights multiply input samples in ascending index order (the printed
+ *    kernels of Sec. 5.2 read that way).
+ *  - fcfs_forward / fcfs_backward enqueue work on the given HIP stream and
+ *    return without waiting. Argument errors are detected before anything is
+ *    enqueued and leave every buffer untouched. A launch failure returns
+ *    FCFS_E_DEVICE; a fault inside a kernel surfaces as FCFS_E_DEVICE from a
+ *    later call that synchronises or from the caller's own stream sync.
+ *  - Plans are immutable after creation and may be shared between threads.
+ *  - No entry point throws; all report through fcfs_status.
+ */
+#ifndef FCFS_H_
+#define FCFS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FCFS_OK = 0,
+  FCFS_E_INVAL = 1,        /* bad argument (sizes, factors, null pointers, layout) */
+  FCFS_E_UNSUPPORTED = 2,  /* valid request outside what this build implements */
+  FCFS_E_NOMEM = 3,        /* host or device allocation failed */
+  FCFS_E_DEVICE = 4,       /* HIP runtime error (launch failure, earlier fault) */
+  FCFS_E_AGAIN = 5,        /* resource busy / queue full, retry later */
+  FCFS_E_PENDING = 6,      /* work not finished yet */
+  FCFS_E_CANCELLED = 7     /* work was cancelled */
+} fcfs_status;
+
+/* Interpolation kernel of each phase (Sec. 5.2). */
+typedef enum {
+  FCFS_NEAREST = 0,     /* Sec. 5.2.1: the sample at floor(u + 1/2); a bit-exact copy */
+  FCFS_BILINEAR = 1,    /* Sec. 5.2.2: 2 taps per axis, weights 1 - t, t */
+  FCFS_BICUBIC = 2,     /* Sec. 5.2.3: 4 taps per axis, Keys cubic, a = -1/2 */
+  FCFS_LEARNED_DW4 = 3, /* learnable depthwise 4x4 taps per phase and channel (Sec. 7) */
+  FCFS_LEARNED_MIX4 = 4 /* learnable 4x4 taps per phase mixing C_in -> C_out channels */
+} fcfs_method;
+
+/* Virtual extension beyond the input's edges (Sec. 3, "Padding"). */
+typedef enum {
+  FCFS_PAD_ZERO = 0,      /* zeros */
+  FCFS_PAD_REPLICATE = 1, /* repetition of the edge sample */
+  FCFS_PAD_REFLECT = 2    /* mirror about the edge sample (edge not repeated), periodic */
+} fcfs_pad;
+
+/* Storage type of x, y, dy and dx. Arithmetic is always FP32. */
+typedef enum { FCFS_F32 = 0, FCFS_BF16 = 1, FCFS_F16 = 2 } fcfs_dtype;
+
+/* Where output sample k = p*m + j samples the input (u in input samples).
+ * HALF : u = (k + 1/2) q/p - 1/2 (pixel centres; identity at p = q).
+ * PAPER: u = (k + 1/2) q/p       (reproduces the 3/2 kernels printed in
+ *                                 Sec. 5.2.1 and Sec. 5.2.2).
+ * ASYM : u = k q/p               (channel j at offset j/p of a cell, the
+ *                                 wording of Sec. 3.1.1). */
+typedef enum { FCFS_GRID_HALF = 0, FCFS_GRID_PAPER = 1, FCFS_GRID_ASYM = 2 } fcfs_grid;
+
+typedef struct fcfs_plan_* fcfs_plan_t;
+
+/* Create a plan for scaling both axes by p/q (Sec. 3.1; Sec. 4.2 with equal
+ * factors), on the half-pixel grid. Host only: builds the per-phase tap
+ * tables (Sec. 5.2) in integer arithmetic, weights rounded once from FP64
+ * to FP32. p and q are reduced by their gcd; after reduction both must be
+ * <= 32. *out receives a plan that the caller frees with fcfs_plan_destroy.
+ * Errors: FCFS_E_INVAL (p < 1, q < 1, bad enum, out == NULL),
+ * FCFS_E_UNSUPPORTED (reduced p or q > 32), FCFS_E_NOMEM. */
+fcfs_status fcfs_plan(int p, int q, fcfs_method method, fcfs_pad pad, fcfs_plan_t* out);
+
+/* As fcfs_plan with a separate factor per axis (Sec. 4.2: r_1/s_1, r_2/s_2)
+ * and a choice of sampling grid. */
+fcfs_status fcfs_plan_ex(int p_h, int q_h, int p_w, int q_w, fcfs_method method, fcfs_pad pad,
+                         fcfs_grid grid, fcfs_plan_t* out);
+
+/* Free a plan. NULL is accepted. */
+fcfs_status fcfs_plan_destroy(fcfs_plan_t plan);
+
+/* Reduced factors of the height axis and taps per axis (1, 2 or 4). Any
+ * output pointer may be NULL. */
+fcfs_status fcfs_plan_query(fcfs_plan_t plan, int* p_red, int* q_red, int* taps);
+
+/* Tap table of one phase (Sec. 3.1.1: phase j of every cell m interpolates
+ * at its own offset; Sec. 5.2: the weights of each method). axis 0 = height,
+ * 1 = width; phase in [0, p_red). Output sample p*m + phase reads input
+ * samples q*m + *first_offset + t for t < taps with weights w[t] (FP32, the
+ * values the kernels use; zeros for learned methods). w must hold 4 floats.
+ * Errors: FCFS_E_INVAL for a bad axis, phase or NULL pointer. */
+fcfs_status fcfs_plan_taps(fcfs_plan_t plan, int axis, int phase, int* first_offset, float* w);
+
+/* Output size for an h x w input: p_h * ceil(h / q_h) by p_w * ceil(w / q_w)
+ * (Sec. 3.1.1 and the 5 -> 9 example of Sec. 5.1). */
+fcfs_status fcfs_output_size(fcfs_plan_t plan, int64_t h, int64_t w, int64_t* h_out, int64_t* w_out);
+
+/* Forward rescale: y = FCFS(x) (Sec. 3.1 / Sec. 4.2 pseudocode).
+ *   x      : device, [n][c_in][h][w] of dtype.
+ *   weight : device FP32. NULL for fixed methods. LEARNED_DW4: [c_in][p_h][p_w][4][4],
+ *            4x4 taps per channel and phase, tap (a, b) reading input row
+ *            q*m_h + floor(u_h) - 1 + a and column q*m_w + floor(u_w) - 1 + b.
+ *            LEARNED_MIX4: [p_h][p_w][c_out][c_in][4][4], same taps, summed over c_in.
+ *   c_out  : output channels; must equal c_in except for LEARNED_MIX4.
+ *   y      : device, [n][c_out][h_out][w_out] of dtype; must not overlap x.
+ *   stream : HIP stream the kernels are enqueued on (0 = the null stream).
+ * An empty problem (n, c_in, h or w equal to 0) is valid and enqueues nothing;
+ * its pointers are not inspected.
+ * Errors: FCFS_E_INVAL (negative sizes, null pointers, weight missing for a learned
+ * method or given for a fixed one, c_out mismatch), FCFS_E_UNSUPPORTED (a
+ * per-plane size at or above 2^31 samples, dtype not built for the method),
+ * FCFS_E_DEVICE (launch failed). */
+fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                         int64_t w, const void* x, const float* weight, int64_t c_out, void* y,
+                         hipStream_t stream);
+
+/* Launch geometry fcfs_forward would use for these sizes (introspection for
+ * tests and benchmarks; enqueues nothing). kernel_id identifies the compiled
+ * kernel instance: dtype*100 + taps*10 + column groups per lane (+ 1000 for
+ * the learned depthwise layer, 2000 for the channel-mixing layer). Any
+ * output pointer may be NULL. Errors: as fcfs_forward's argument checks. */
+fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
+                                int64_t h, int64_t w, int* kernel_id, int* strip_width,
+                                int* band_cells, int64_t* waves);
+
+/* Device workspace bytes fcfs_backward needs for these sizes (0 if none). */
+fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
+                                    int64_t h, int64_t w, int64_t c_out, size_t* bytes);
+
+/* Backward (the adjoint of fcfs_forward, for training the layer of Sec. 7).
+ *   dy : device [n][c_out][h_out][w_out] of dtype, the gradient of y.
+ *   dx : device [n][c_in][h][w] of dtype or NULL: receives A^T dy, i.e. for
+ *        each input sample the sum of w * dy over every (output, tap) that
+ *        read it, padding folded back (replicate: onto the edge sample;
+ *        reflect: onto the mirrored sample; zero: dropped). Overwritten.
+ *   dw : device FP32, same layout as weight, or NULL: receives the weight
+ *        gradient sum over n and cells of dy * (padded x). Learned methods
+ *        only. Overwritten (not accumulated). Deterministic: the summation
+ *        order is fixed by the sizes alone.
+ *   x  : needed iff dw != NULL. weight: needed for learned methods iff dx != NULL.
+ *   workspace / ws_bytes: device scratch of at least fcfs_backward_workspace
+ *        bytes (NULL allowed when that is 0).
+ * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small. */
+fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                          int64_t w, const void* x, const float* weight, int64_t c_out,
+                          const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Static text for a status code. */
+const char* fcfs_status_string(fcfs_status status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int fcfs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCFS_H_ */

@@ -59,6 +59,8 @@ def _load():
             lib.fcfs_oracle_phase_kernel.restype = L
             lib.fcfs_oracle_forward.argtypes = [L, L, L, L, I, I, I, L, L, L, L, P, P, L, P]
             lib.fcfs_oracle_forward.restype = I
+            lib.fcfs_oracle_forward_absw.argtypes = lib.fcfs_oracle_forward.argtypes
+            lib.fcfs_oracle_forward_absw.restype = I
             lib.fcfs_oracle_backward.argtypes = [L, L, L, L, I, I, I, L, L, L, L, P, P, L, P, P, P]
             lib.fcfs_oracle_backward.restype = I
             lib.fcfs_oracle_threads.argtypes = []
@@ -99,11 +101,12 @@ def phase_kernel(p: int, q: int, method: str, grid: str, j: int) -> np.ndarray:
 
 
 def forward(x, p, q, method="bilinear", pad="replicate", grid="half", weight=None,
-            cout=None, pw=None, qw=None) -> np.ndarray:
+            cout=None, pw=None, qw=None, abs_weights=False) -> np.ndarray:
     """FCFS forward of an NCHW array in FP64.
 
     ``p/q`` scales both axes unless ``pw/qw`` gives the width factor.
     ``weight``: dw4 [C, ph, pw, 4, 4]; mix4 [ph, pw, Cout, Cin, 4, 4].
+    ``abs_weights``: use |w| for every tap (see ``condition``).
     """
     x = _f64(x)
     if x.ndim != 4:
@@ -115,11 +118,20 @@ def forward(x, p, q, method="bilinear", pad="replicate", grid="half", weight=Non
     Ho, Wo = out_len(ph, qh, H), out_len(pw_, qw_, W)
     y = np.empty((N, co, Ho, Wo), dtype=np.float64)
     w = _f64(weight)
-    rc = _load().fcfs_oracle_forward(ph, qh, pw_, qw_, m, PADS[pad], GRIDS[grid], N, C, H, W,
-                                     _ptr(x), _ptr(w), co, _ptr(y))
+    fn = _load().fcfs_oracle_forward_absw if abs_weights else _load().fcfs_oracle_forward
+    rc = fn(ph, qh, pw_, qw_, m, PADS[pad], GRIDS[grid], N, C, H, W, _ptr(x), _ptr(w), co, _ptr(y))
     if rc != 0:
         raise ValueError("oracle forward rejected its arguments")
     return y
+
+
+def condition(x, p, q, method="bilinear", pad="replicate", grid="half", weight=None,
+              cout=None, pw=None, qw=None) -> np.ndarray:
+    """Per-output scale S = sum over taps of |w| * |x| (same shape as the
+    output), the size a rounding error of each output's dot product is
+    measured against."""
+    return forward(np.abs(np.asarray(x, dtype=np.float64)), p, q, method, pad, grid, weight,
+                   cout, pw, qw, abs_weights=True)
 
 
 def backward(dy, x_shape, p, q, method="bilinear", pad="replicate", grid="half", x=None,

@@ -169,7 +169,7 @@ static int o_geom_init(o_geom* g, long rh, long sh, long rw, long sw, long H, lo
  * are separable); for dw4 it holds W[c][jh][jw] placed at its anchor; for mix4
  * W[jh][jw][o][c]. Layout: ker[((grp * P + ph) * KH + kh) * KW + kw]. */
 static double* o_build_kernels(const o_geom* g, int method, int grid, const double* weight,
-                               long cin, long cout, long* ngroups_out) {
+                               long cin, long cout, long* ngroups_out, int absw) {
   long KH = 2 * g->Kh + 1, KW = 2 * g->Kw + 1;
   long ngroups = 1;
   if (method == OM_DW4) ngroups = cin;
@@ -186,7 +186,7 @@ static double* o_build_kernels(const o_geom* g, int method, int grid, const doub
         fcfs_oracle_phase_kernel(g->rw, g->sw, method, grid, jw, hw);
         double* k = ker + (jh * g->rw + jw) * KH * KW;
         for (long a = 0; a < KH; ++a)
-          for (long b = 0; b < KW; ++b) k[a * KW + b] = hh[a] * hw[b];
+          for (long b = 0; b < KW; ++b) k[a * KW + b] = absw ? fabs(hh[a] * hw[b]) : hh[a] * hw[b];
       }
     }
     free(hh); free(hw);
@@ -208,7 +208,7 @@ static double* o_build_kernels(const o_geom* g, int method, int grid, const doub
         for (long a = 0; a < 4; ++a)
           for (long b = 0; b < 4; ++b) {
             long kh = -(ah + a), kw = -(aw + b);   /* offset o = -k */
-            k[(g->Kh + kh) * KW + (g->Kw + kw)] = w4[a * 4 + b];
+            k[(g->Kh + kh) * KW + (g->Kw + kw)] = absw ? fabs(w4[a * 4 + b]) : w4[a * 4 + b];
           }
       }
     }
@@ -247,16 +247,16 @@ static double o_conv_at(const o_geom* g, const double* xp, const double* k, long
  * weight: dw4 [Cin][rh][rw][4][4]; mix4 [rh][rw][Cout][Cin][4][4]; else unused.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-int fcfs_oracle_forward(long rh, long sh, long rw, long sw, int method, int pad, int grid,
-                        long N, long Cin, long H, long W, const double* x,
-                        const double* weight, long Cout, double* y) {
+static int o_forward(long rh, long sh, long rw, long sw, int method, int pad, int grid,
+                     long N, long Cin, long H, long W, const double* x,
+                     const double* weight, long Cout, double* y, int absw) {
   o_geom g;
   if (o_geom_init(&g, rh, sh, rw, sw, H, W)) return -1;
   if (method < 0 || method > OM_MIX4 || pad < 0 || pad > OP_REFLECT || grid < 0 || grid > OG_ASYM) return -1;
   if (method != OM_MIX4) Cout = Cin;
   if ((method == OM_DW4 || method == OM_MIX4) && !weight) return -1;
   long ngroups;
-  double* ker = o_build_kernels(&g, method, grid, weight, Cin, Cout, &ngroups);
+  double* ker = o_build_kernels(&g, method, grid, weight, Cin, Cout, &ngroups, absw);
   if (!ker) return -1;
   long KHW = (2 * g.Kh + 1) * (2 * g.Kw + 1);
   long plane_in = H * W, plane_p = g.Hp * g.Wp, cells = g.Mh * g.Mw;
@@ -305,6 +305,22 @@ int fcfs_oracle_forward(long rh, long sh, long rw, long sw, int method, int pad,
   return 0;
 }
 
+int fcfs_oracle_forward(long rh, long sh, long rw, long sw, int method, int pad, int grid,
+                        long N, long Cin, long H, long W, const double* x,
+                        const double* weight, long Cout, double* y) {
+  return o_forward(rh, sh, rw, sw, method, pad, grid, N, Cin, H, W, x, weight, Cout, y, 0);
+}
+
+/* Conditioning of each output for error bounds: the same pipeline with every
+ * kernel tap replaced by its absolute value. Called with |x| it gives
+ * S = sum over taps of |w| |x|, the scale a rounding error of the output's
+ * dot product is measured against. */
+int fcfs_oracle_forward_absw(long rh, long sh, long rw, long sw, int method, int pad, int grid,
+                             long N, long Cin, long H, long W, const double* x,
+                             const double* weight, long Cout, double* y) {
+  return o_forward(rh, sh, rw, sw, method, pad, grid, N, Cin, H, W, x, weight, Cout, y, 1);
+}
+
 /*
  * Backward: the adjoint of the forward pipeline.
  * dy: [N][Cout][Ho][Wo]. dx (nullable): [N][Cin][H][W]. dw (nullable, dw4/mix4
@@ -322,7 +338,7 @@ int fcfs_oracle_backward(long rh, long sh, long rw, long sw, int method, int pad
   if (learned && !weight) return -1;
   if (dw && (!learned || !x)) return -1;
   long ngroups;
-  double* ker = o_build_kernels(&g, method, grid, weight, Cin, Cout, &ngroups);
+  double* ker = o_build_kernels(&g, method, grid, weight, Cin, Cout, &ngroups, 0);
   if (!ker) return -1;
   long KH = 2 * g.Kh + 1, KW = 2 * g.Kw + 1, KHW = KH * KW;
   long plane_in = H * W, plane_p = g.Hp * g.Wp, cells = g.Mh * g.Mw;

@@ -1,0 +1,291 @@
+"""Python binding of libfcfs: fully convolutional fractional scaling on MI355X.
+
+Thin ctypes marshalling over the C ABI declared in ``include/fcfs.h``; every
+step of the computation runs in the library's HIP kernels. PyTorch supplies
+device memory (its caching allocator) and the stream work is enqueued on.
+
+Low-level functions carry the C names (``fcfs_plan``, ``fcfs_forward``, ...)
+and take plain integers / pointers. The convenience layer on top
+(``Plan``, ``resize``, ``FCFSFunction``) converts torch tensors to pointers.
+
+There is no fallback: if ``libfcfs.so`` is missing, importing this package
+raises, and every call requires tensors that live on a ROCm device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "FcfsError", "METHODS", "PADS", "GRIDS", "DTYPES", "lib", "library_path",
+    "fcfs_plan", "fcfs_plan_ex", "fcfs_plan_destroy", "fcfs_plan_query", "fcfs_plan_taps",
+    "fcfs_output_size",
+    "fcfs_forward", "fcfs_forward_config", "fcfs_backward_workspace", "fcfs_backward", "fcfs_status_string",
+    "fcfs_version", "Plan", "resize", "FCFSFunction",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libfcfs.so")
+
+METHODS = {"nearest": 0, "bilinear": 1, "bicubic": 2, "dw4": 3, "mix4": 4}
+PADS = {"zero": 0, "replicate": 1, "reflect": 2}
+GRIDS = {"half": 0, "paper": 1, "asym": 2}
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+
+OK, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_AGAIN, E_PENDING, E_CANCELLED = range(8)
+
+
+class FcfsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, fcfs_status_string(status), status))
+
+
+def _load():
+    if not os.path.exists(library_path):
+        raise ImportError("libfcfs.so is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "or `python paper_2203_10670_amd/build.py` first (%s)" % library_path)
+    return ctypes.CDLL(library_path)
+
+
+lib = _load()
+
+_I, _I64, _P, _SZ = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def _sig(name, args, res=_I):
+    f = getattr(lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("fcfs_plan", [_I, _I, _I, _I, _PP])
+_sig("fcfs_plan_ex", [_I, _I, _I, _I, _I, _I, _I, _PP])
+_sig("fcfs_plan_destroy", [_P])
+_sig("fcfs_plan_query", [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)])
+_sig("fcfs_plan_taps", [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float)])
+_sig("fcfs_output_size", [_P, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)])
+_sig("fcfs_forward", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P])
+_sig("fcfs_forward_config", [_P, _I, _I64, _I64, _I64, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                             ctypes.POINTER(_I), ctypes.POINTER(_I64)])
+_sig("fcfs_backward_workspace", [_P, _I, _I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)])
+_sig("fcfs_backward", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P])
+_sig("fcfs_status_string", [_I], ctypes.c_char_p)
+_sig("fcfs_version", [], _I)
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise FcfsError(status, where)
+
+
+# ------------------------------------------------------------------ C names
+
+def fcfs_status_string(status: int) -> str:
+    return lib.fcfs_status_string(status).decode()
+
+
+def fcfs_version() -> int:
+    return lib.fcfs_version()
+
+
+def fcfs_plan(p: int, q: int, method: int, pad: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.fcfs_plan(p, q, method, pad, ctypes.byref(h)), "fcfs_plan")
+    return h.value
+
+
+def fcfs_plan_ex(p_h: int, q_h: int, p_w: int, q_w: int, method: int, pad: int, grid: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.fcfs_plan_ex(p_h, q_h, p_w, q_w, method, pad, grid, ctypes.byref(h)), "fcfs_plan_ex")
+    return h.value
+
+
+def fcfs_plan_destroy(plan: int) -> None:
+    _check(lib.fcfs_plan_destroy(plan), "fcfs_plan_destroy")
+
+
+def fcfs_plan_query(plan: int):
+    p, q, t = _I(), _I(), _I()
+    _check(lib.fcfs_plan_query(plan, ctypes.byref(p), ctypes.byref(q), ctypes.byref(t)), "fcfs_plan_query")
+    return p.value, q.value, t.value
+
+
+def fcfs_plan_taps(plan: int, axis: int, phase: int):
+    """(first tap offset, [4 weights]) of one phase of one axis."""
+    off = _I()
+    w = (ctypes.c_float * 4)()
+    _check(lib.fcfs_plan_taps(plan, axis, phase, ctypes.byref(off), w), "fcfs_plan_taps")
+    return off.value, list(w)
+
+
+def fcfs_output_size(plan: int, h: int, w: int):
+    ho, wo = _I64(), _I64()
+    _check(lib.fcfs_output_size(plan, h, w, ctypes.byref(ho), ctypes.byref(wo)), "fcfs_output_size")
+    return ho.value, wo.value
+
+
+def fcfs_forward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, y_ptr, stream) -> int:
+    """Returns the raw status (callers decide whether to raise)."""
+    return lib.fcfs_forward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, y_ptr, stream)
+
+
+def fcfs_forward_config(plan, dtype, n, c_in, h, w):
+    """(kernel_id, strip_width, band_cells, waves) of the forward launch."""
+    k, tw, bc, wv = _I(), _I(), _I(), _I64()
+    _check(lib.fcfs_forward_config(plan, dtype, n, c_in, h, w, ctypes.byref(k), ctypes.byref(tw),
+                                   ctypes.byref(bc), ctypes.byref(wv)), "fcfs_forward_config")
+    return k.value, tw.value, bc.value, wv.value
+
+
+def fcfs_backward_workspace(plan, dtype, n, c_in, h, w, c_out) -> int:
+    b = _SZ()
+    _check(lib.fcfs_backward_workspace(plan, dtype, n, c_in, h, w, c_out, ctypes.byref(b)),
+           "fcfs_backward_workspace")
+    return b.value
+
+
+def fcfs_backward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, dx_ptr, dw_ptr,
+                  ws_ptr, ws_bytes, stream) -> int:
+    return lib.fcfs_backward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, dx_ptr,
+                             dw_ptr, ws_ptr, ws_bytes, stream)
+
+
+# ------------------------------------------------------------------ torch layer
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.float32: 0, torch.bfloat16: 1, torch.float16: 2}
+    if t.dtype not in m:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+def _stream_ptr(device) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libfcfs takes device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous NCHW")
+    return t.data_ptr()
+
+
+class Plan:
+    """Owns an fcfs plan handle."""
+
+    def __init__(self, p: int, q: int, method: str = "bilinear", pad: str = "replicate",
+                 grid: str = "half", pw: int | None = None, qw: int | None = None):
+        self.method, self.pad, self.grid = method, pad, grid
+        self.p, self.q = p, q
+        self.pw = p if pw is None else pw
+        self.qw = q if qw is None else qw
+        self.handle = fcfs_plan_ex(p, q, self.pw, self.qw, METHODS[method], PADS[pad], GRIDS[grid])
+        self.p_red, self.q_red, self.taps = fcfs_plan_query(self.handle)
+
+    def output_size(self, h: int, w: int):
+        return fcfs_output_size(self.handle, h, w)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.fcfs_plan_destroy(h)
+            self.handle = None
+
+    # forward / backward on torch tensors -------------------------------
+    def forward(self, x, weight=None, out=None):
+        torch = _torch()
+        n, c, h, w = x.shape
+        ho, wo = self.output_size(h, w)
+        c_out = c
+        if self.method == "mix4":
+            c_out = weight.shape[2]
+        if out is None:
+            out = torch.empty((n, c_out, ho, wo), dtype=x.dtype, device=x.device)
+        st = fcfs_forward(self.handle, _dtype_code(x), n, c, h, w, _dev_ptr(x), _dev_ptr(weight),
+                          c_out, _dev_ptr(out), _stream_ptr(x.device))
+        _check(st, "fcfs_forward")
+        return out
+
+    def backward(self, dy, x_shape, x=None, weight=None, need_dx=True, need_dw=False):
+        torch = _torch()
+        n, c, h, w = x_shape
+        c_out = dy.shape[1]
+        dx = torch.empty((n, c, h, w), dtype=dy.dtype, device=dy.device) if need_dx else None
+        dw = torch.empty_like(weight, dtype=torch.float32) if need_dw else None
+        code = _dtype_code(dy)
+        ws_bytes = fcfs_backward_workspace(self.handle, code, n, c, h, w, c_out)
+        ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dy.device)
+        st = fcfs_backward(self.handle, code, n, c, h, w, _dev_ptr(x), _dev_ptr(weight), c_out,
+                           _dev_ptr(dy), _dev_ptr(dx), _dev_ptr(dw), _dev_ptr(ws), ws_bytes,
+                           _stream_ptr(dy.device))
+        _check(st, "fcfs_backward")
+        return dx, dw
+
+
+_plan_cache: dict = {}
+
+
+def _cached_plan(p, q, method, pad, grid, pw, qw):
+    key = (p, q, method, pad, grid, pw, qw)
+    pl = _plan_cache.get(key)
+    if pl is None:
+        pl = _plan_cache[key] = Plan(p, q, method, pad, grid, pw, qw)
+    return pl
+
+
+def resize(x, p: int, q: int, method: str = "bilinear", pad: str = "replicate", grid: str = "half",
+           weight=None, pw: int | None = None, qw: int | None = None):
+    """Rescale an NCHW device tensor by p/q (and pw/qw on the width axis)."""
+    return _cached_plan(p, q, method, pad, grid, pw, qw).forward(x.contiguous(), weight)
+
+
+def _make_function():
+    torch = _torch()
+
+    class FCFSFunction(torch.autograd.Function):
+        """Differentiable FCFS layer: forward and backward run in libfcfs."""
+
+        @staticmethod
+        def forward(ctx, x, weight, plan: Plan):
+            x = x.contiguous()
+            w = weight.contiguous() if weight is not None else None
+            ctx.plan = plan
+            ctx.x_shape = tuple(x.shape)
+            ctx.save_for_backward(x, w)
+            return plan.forward(x, w)
+
+        @staticmethod
+        def backward(ctx, dy):
+            x, w = ctx.saved_tensors
+            need_dx = ctx.needs_input_grad[0]
+            need_dw = w is not None and ctx.needs_input_grad[1]
+            dx, dw = ctx.plan.backward(dy.contiguous(), ctx.x_shape, x=x if need_dw else None,
+                                       weight=w, need_dx=need_dx, need_dw=need_dw)
+            return dx, dw, None
+
+    return FCFSFunction
+
+
+class _LazyFunction:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyFunction._cls is None:
+            _LazyFunction._cls = _make_function()
+        return getattr(_LazyFunction._cls, name)
+
+
+FCFSFunction = _LazyFunction()

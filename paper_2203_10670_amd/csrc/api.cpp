@@ -1,0 +1,342 @@
+// C ABI of libfcfs: plans (per-axis tap tables), argument validation and
+// dispatch to the HIP kernels.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fcfs_internal.h"
+
+namespace fcfs {
+namespace {
+
+int64_t floor_div(int64_t a, int64_t b) {
+  int64_t d = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --d;
+  return d;
+}
+
+int gcd_int(int a, int b) {
+  while (b) {
+    int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+int mod_pos(int a, int q) {
+  int m = a % q;
+  return m < 0 ? m + q : m;
+}
+
+// Keys cubic convolution weights (a = -1/2, paper Sec. 5.2.3) of the four
+// samples at offsets -1, 0, 1, 2 from floor(u), for fractional part t.
+void keys_taps(double t, double w[4]) {
+  const double t2 = t * t, t3 = t2 * t;
+  w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+  w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+  w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+  w[3] = 0.5 * (t3 - t2);
+}
+
+// Overflow-checked product.
+bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+  if (a < 0 || b < 0) return false;
+  if (a != 0 && b > INT64_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+}  // namespace
+
+// Sampling position of phase j of a cell, as a numerator over 2p of the
+// offset from q*m (paper Sec. 3.1.1: each of the p kernels interpolates at
+// its own sub-cell offset), for each grid reading.
+static int64_t grid_numerator(int p, int q, int j, int grid) {
+  switch (grid) {
+    case FCFS_GRID_PAPER: return (int64_t)(2 * j + 1) * q;
+    case FCFS_GRID_ASYM: return (int64_t)2 * j * q;
+    default: return (int64_t)(2 * j + 1) * q - p;
+  }
+}
+
+fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, AxisTable* t) {
+  std::memset(t, 0, sizeof(*t));
+  const int g = gcd_int(p, q);
+  p /= g;
+  q /= g;
+  if (p > kMaxFactor || q > kMaxFactor) return FCFS_E_UNSUPPORTED;
+  t->p = p;
+  t->q = q;
+  const bool learned = method == FCFS_LEARNED_DW4 || method == FCFS_LEARNED_MIX4;
+  // At 1/1 the half and asym grids sample every input exactly: a copy.
+  const bool identity = allow_copy && !learned && p == 1 && q == 1 && grid != FCFS_GRID_PAPER;
+  int T = 4;
+  if (!learned) {
+    if (method == FCFS_NEAREST || identity) T = 1;
+    else if (method == FCFS_BILINEAR) T = 2;
+  }
+  t->T = T;
+  int omin = 1 << 30, omax = -(1 << 30);
+  for (int j = 0; j < p; ++j) {
+    const int64_t A = grid_numerator(p, q, j, grid);
+    const int64_t two_p = 2 * (int64_t)p;
+    const int64_t b = floor_div(A, two_p);
+    const double frac = (double)(A - two_p * b) / (double)two_p;
+    int off;
+    double w[4] = {0, 0, 0, 0};
+    if (T == 1) {
+      off = (int)floor_div(A + p, two_p);   // floor(u + 1/2)
+      w[0] = 1.0;
+    } else if (T == 2) {
+      off = (int)b;
+      w[0] = 1.0 - frac;
+      w[1] = frac;
+    } else {
+      off = (int)b - 1;
+      if (!learned) keys_taps(frac, w);
+    }
+    t->off[j] = (int8_t)off;
+    for (int k = 0; k < 4; ++k) t->w[j][k] = (float)w[k];
+    omin = std::min(omin, off);
+    omax = std::max(omax, off + T - 1);
+  }
+  t->omin = omin;
+  t->omax = omax;
+  uint32_t mask = 0;
+  for (int j = 0; j < p; ++j)
+    for (int k = 0; k < T; ++k) mask |= 1u << mod_pos(t->off[j] + k, q);
+  t->need_mask = mask;
+  int n = 0;
+  for (int r = 0; r < q; ++r) {
+    t->emit_start[r] = (uint8_t)n;
+    for (int j = 0; j < p; ++j)
+      if (mod_pos(t->off[j] + T - 1, q) == r) t->emit_list[n++] = (uint8_t)j;
+  }
+  t->emit_start[q] = (uint8_t)n;
+  return FCFS_OK;
+}
+
+fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
+                              FwdGeom* g) {
+  (void)h;
+  (void)w;
+  const AxisTable& aw = plan->aw;
+  const AxisTable& ah = plan->ah;
+  const int span = aw.omax - aw.omin + 1;
+  const int cap = 512;   // staged row segment per wave (kRowDwords * 64)
+  auto seg = [&](int tw) { return aw.q * ((tw + aw.p - 2) / aw.p) + span; };
+  const bool learned = plan->method == FCFS_LEARNED_DW4;
+  int kc = learned ? 1 : 4;
+  while (kc > 1 && (seg(64 * kc) > cap || wo <= 64 * (kc / 2))) kc /= 2;
+  int tw = 64 * kc;
+  while (tw > 1 && seg(tw) > cap) tw /= 2;
+  if (seg(tw) > cap) return FCFS_E_UNSUPPORTED;
+  g->kc = kc;
+  g->tw = tw;
+  g->strips = (wo + tw - 1) / tw;
+  const int Mh = ho / ah.p;
+  // Enough waves to fill 256 CUs several times over; bands of at least two cells.
+  const int64_t target_waves = 16384;
+  const int64_t per_band = planes * g->strips;
+  int64_t bands = (target_waves + per_band - 1) / per_band;
+  bands = std::max<int64_t>(1, std::min<int64_t>(bands, std::max(1, Mh / 2)));
+  int band_cells = (int)((Mh + bands - 1) / bands);
+  g->band_cells = band_cells;
+  g->bands = (Mh + band_cells - 1) / band_cells;
+  g->waves = planes * g->strips * (int64_t)g->bands;
+  return FCFS_OK;
+}
+
+}  // namespace fcfs
+
+using namespace fcfs;
+
+extern "C" {
+
+fcfs_status fcfs_plan_ex(int p_h, int q_h, int p_w, int q_w, fcfs_method method, fcfs_pad pad,
+                         fcfs_grid grid, fcfs_plan_t* out) {
+  if (!out) return FCFS_E_INVAL;
+  *out = nullptr;
+  if (p_h < 1 || q_h < 1 || p_w < 1 || q_w < 1) return FCFS_E_INVAL;
+  if ((int)method < FCFS_NEAREST || (int)method > FCFS_LEARNED_MIX4) return FCFS_E_INVAL;
+  if ((int)pad < FCFS_PAD_ZERO || (int)pad > FCFS_PAD_REFLECT) return FCFS_E_INVAL;
+  if ((int)grid < FCFS_GRID_HALF || (int)grid > FCFS_GRID_ASYM) return FCFS_E_INVAL;
+  fcfs_plan_* pl = new (std::nothrow) fcfs_plan_();
+  if (!pl) return FCFS_E_NOMEM;
+  pl->method = method;
+  pl->pad = pad;
+  pl->grid = grid;
+  fcfs_status st = build_axis(p_h, q_h, method, grid, true, &pl->ah);
+  if (st == FCFS_OK) st = build_axis(p_w, q_w, method, grid, true, &pl->aw);
+  if (st == FCFS_OK && pl->ah.T != pl->aw.T) {
+    // Only the 1/1 copy shortcut makes the axes differ: the kernel takes one
+    // tap count, so give both axes the method's full taps.
+    st = build_axis(p_h, q_h, method, grid, false, &pl->ah);
+    if (st == FCFS_OK) st = build_axis(p_w, q_w, method, grid, false, &pl->aw);
+  }
+  if (st != FCFS_OK) {
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_plan(int p, int q, fcfs_method method, fcfs_pad pad, fcfs_plan_t* out) {
+  return fcfs_plan_ex(p, q, p, q, method, pad, FCFS_GRID_HALF, out);
+}
+
+fcfs_status fcfs_plan_destroy(fcfs_plan_t plan) {
+  delete plan;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_plan_query(fcfs_plan_t plan, int* p_red, int* q_red, int* taps) {
+  if (!plan) return FCFS_E_INVAL;
+  if (p_red) *p_red = plan->ah.p;
+  if (q_red) *q_red = plan->ah.q;
+  if (taps) *taps = plan->ah.T;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_plan_taps(fcfs_plan_t plan, int axis, int phase, int* first_offset, float* w) {
+  if (!plan || !first_offset || !w || (axis != 0 && axis != 1)) return FCFS_E_INVAL;
+  const AxisTable& t = axis == 0 ? plan->ah : plan->aw;
+  if (phase < 0 || phase >= t.p) return FCFS_E_INVAL;
+  *first_offset = t.off[phase];
+  for (int k = 0; k < 4; ++k) w[k] = k < t.T ? t.w[phase][k] : 0.f;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_output_size(fcfs_plan_t plan, int64_t h, int64_t w, int64_t* h_out, int64_t* w_out) {
+  if (!plan || h < 1 || w < 1) return FCFS_E_INVAL;
+  const int64_t cells_h = (h + plan->ah.q - 1) / plan->ah.q;
+  const int64_t cells_w = (w + plan->aw.q - 1) / plan->aw.q;
+  if (h_out) *h_out = plan->ah.p * cells_h;
+  if (w_out) *w_out = plan->aw.p * cells_w;
+  return FCFS_OK;
+}
+
+static fcfs_status check_common(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                                 int64_t w, int64_t c_out, int64_t* ho, int64_t* wo) {
+  if (!plan) return FCFS_E_INVAL;
+  if ((int)dtype < FCFS_F32 || (int)dtype > FCFS_F16) return FCFS_E_INVAL;
+  if (n < 0 || c_in < 0 || h < 0 || w < 0 || c_out < 0) return FCFS_E_INVAL;
+  if (plan->method != FCFS_LEARNED_MIX4 && c_out != c_in) return FCFS_E_INVAL;
+  *ho = plan->ah.p * ((h + plan->ah.q - 1) / plan->ah.q);
+  *wo = plan->aw.p * ((w + plan->aw.q - 1) / plan->aw.q);
+  int64_t in_plane, out_plane, tmp;
+  if (!mul_ok(h, w, &in_plane) || !mul_ok(*ho, *wo, &out_plane)) return FCFS_E_UNSUPPORTED;
+  if (in_plane >= (1LL << 31) || out_plane >= (1LL << 31) || *ho >= (1LL << 31) || *wo >= (1LL << 31))
+    return FCFS_E_UNSUPPORTED;
+  if (!mul_ok(n, c_in, &tmp) || !mul_ok(tmp, in_plane, &tmp)) return FCFS_E_INVAL;
+  if (!mul_ok(n, c_out, &tmp) || !mul_ok(tmp, out_plane, &tmp)) return FCFS_E_INVAL;
+  if (c_in >= (1LL << 31) || c_out >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                         int64_t w, const void* x, const float* weight, int64_t c_out, void* y,
+                         hipStream_t stream) {
+  int64_t ho = 0, wo = 0;
+  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
+  if (st != FCFS_OK) return st;
+  const bool learned = plan->method == FCFS_LEARNED_DW4 || plan->method == FCFS_LEARNED_MIX4;
+  if (n == 0 || c_in == 0 || c_out == 0 || h == 0 || w == 0) return FCFS_OK;   // nothing to do
+  if (!x || !y) return FCFS_E_INVAL;
+  if (learned != (weight != nullptr)) return FCFS_E_INVAL;
+  if (plan->method == FCFS_LEARNED_MIX4) return FCFS_E_UNSUPPORTED;
+  if (plan->method == FCFS_LEARNED_DW4 && plan->ah.p * plan->aw.p > 64) return FCFS_E_UNSUPPORTED;
+
+  FwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.y = y;
+  a.weight = weight;
+  a.planes = n * c_in;
+  a.C = (int)c_in;
+  a.H = (int)h;
+  a.W = (int)w;
+  a.Ho = (int)ho;
+  a.Wo = (int)wo;
+  a.Mh = (int)(ho / plan->ah.p);
+  a.pad = plan->pad;
+  a.th = plan->ah;
+  a.tw_tab = plan->aw;
+  FwdGeom g;
+  st = plan_forward_geom(plan, a.planes, a.H, a.W, a.Ho, a.Wo, &g);
+  if (st != FCFS_OK) return st;
+  a.tw = g.tw;
+  a.strips = g.strips;
+  a.band_cells = g.band_cells;
+  a.bands = g.bands;
+  a.waves = g.waves;
+  return launch_forward_fixed(plan, dtype, a, g, stream);
+}
+
+fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
+                                int64_t h, int64_t w, int* kernel_id, int* strip_width,
+                                int* band_cells, int64_t* waves) {
+  int64_t ho = 0, wo = 0;
+  const int64_t c_out = (plan && plan->method == FCFS_LEARNED_MIX4) ? 1 : c_in;
+  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
+  if (st != FCFS_OK) return st;
+  FwdGeom g;
+  std::memset(&g, 0, sizeof(g));
+  if (n > 0 && c_in > 0 && h > 0 && w > 0) {
+    st = plan_forward_geom(plan, n * c_in, (int)h, (int)w, (int)ho, (int)wo, &g);
+    if (st != FCFS_OK) return st;
+  }
+  int id = (int)dtype * 100 + plan->ah.T * 10 + g.kc;
+  if (plan->method == FCFS_LEARNED_DW4) id += 1000;
+  if (plan->method == FCFS_LEARNED_MIX4) id += 2000;
+  if (kernel_id) *kernel_id = id;
+  if (strip_width) *strip_width = g.tw;
+  if (band_cells) *band_cells = g.band_cells;
+  if (waves) *waves = g.waves;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
+                                    int64_t h, int64_t w, int64_t c_out, size_t* bytes) {
+  int64_t ho = 0, wo = 0;
+  if (!bytes) return FCFS_E_INVAL;
+  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
+  if (st != FCFS_OK) return st;
+  *bytes = 0;
+  return FCFS_E_UNSUPPORTED;
+}
+
+fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                          int64_t w, const void* x, const float* weight, int64_t c_out,
+                          const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
+                          hipStream_t stream) {
+  (void)x; (void)weight; (void)dy; (void)dx; (void)dw; (void)workspace; (void)ws_bytes; (void)stream;
+  int64_t ho = 0, wo = 0;
+  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
+  if (st != FCFS_OK) return st;
+  return FCFS_E_UNSUPPORTED;
+}
+
+const char* fcfs_status_string(fcfs_status s) {
+  switch (s) {
+    case FCFS_OK: return "ok";
+    case FCFS_E_INVAL: return "invalid argument";
+    case FCFS_E_UNSUPPORTED: return "unsupported";
+    case FCFS_E_NOMEM: return "out of memory";
+    case FCFS_E_DEVICE: return "device error";
+    case FCFS_E_AGAIN: return "busy, try again";
+    case FCFS_E_PENDING: return "pending";
+    case FCFS_E_CANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+int fcfs_version(void) { return 100; }
+
+}  // extern "C"

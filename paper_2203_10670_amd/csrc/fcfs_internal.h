@@ -1,0 +1,73 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/fcfs.h"
+
+namespace fcfs {
+
+constexpr int kMaxFactor = 32;   // largest reduced p or q a plan accepts
+
+// Per-axis tap table of a plan (paper Sec. 3.1.1 and Sec. 5.2): output sample
+// k = p*m + j reads input samples q*m + off[j] + t, t = 0..T-1, with weights
+// w[j][t]. Passed to kernels by value (it lives in the kernel-argument
+// segment).
+struct AxisTable {
+  int p, q;                  // reduced factor
+  int T;                     // taps: 1 nearest, 2 bilinear, 4 bicubic / learned
+  int omin, omax;            // smallest first tap and largest last tap offset
+  uint32_t need_mask;        // bit r: some tap reads an input index = r (mod q)
+  int8_t off[kMaxFactor];    // first tap offset of each phase (in [-2, q])
+  uint8_t emit_start[kMaxFactor + 1];  // phases whose last tap is = r (mod q):
+  uint8_t emit_list[kMaxFactor];       //   emit_list[emit_start[r] .. emit_start[r+1])
+  float w[kMaxFactor][4];    // tap weights (fixed methods; unused when learned)
+};
+
+}  // namespace fcfs
+
+struct fcfs_plan_ {
+  int method;   // fcfs_method
+  int pad;      // fcfs_pad
+  int grid;     // fcfs_grid
+  fcfs::AxisTable ah, aw;
+};
+
+namespace fcfs {
+
+// Builds one axis table; returns FCFS_OK or an error.
+// allow_copy: at 1/1 on a grid that samples inputs exactly, use one tap.
+fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, AxisTable* out);
+
+// Launch geometry of the fused forward kernel.
+struct FwdGeom {
+  int kc;            // output-column groups per lane (1, 2 or 4)
+  int tw;            // output columns per wave strip
+  int strips;        // strips per plane
+  int band_cells;    // hidden-layer cells (row groups) per wave band
+  int bands;         // bands per plane
+  int64_t waves;     // total waves
+};
+
+struct FwdArgs {
+  const void* x;
+  void* y;
+  const float* weight;   // learned depthwise taps [C][p_h][p_w][4][4] or null
+  int64_t planes;        // n * c
+  int C;
+  int H, W, Ho, Wo, Mh;
+  int pad;
+  int tw, strips, band_cells, bands;
+  int64_t waves;
+  AxisTable th, tw_tab;
+};
+
+// Kernel launchers (fwd.hip). dtype: fcfs_dtype.
+fcfs_status launch_forward_fixed(const fcfs_plan_* plan, int dtype, const FwdArgs& a,
+                                 const FwdGeom& g, hipStream_t stream);
+
+// Host-side launch geometry for a plane of (h, w) -> (ho, wo).
+fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho,
+                              int wo, FwdGeom* g);
+
+}  // namespace fcfs

@@ -1,0 +1,116 @@
+"""Host-side checks of libfcfs that need no GPU: the library loads, exports
+every entry point its header declares, validates arguments, and its plan
+tables (built by the library's own integer code) agree with the oracle's
+dense per-phase kernels."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2203_10670_amd as fc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(fcfs_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(fc.library_path)
+    out = subprocess.run(["nm", "-D", "--defined-only", fc.library_path], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (fcfs_\w+)", out))
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in exported, n
+
+
+def test_status_strings_and_version():
+    assert fc.fcfs_status_string(0) == "ok"
+    assert "invalid" in fc.fcfs_status_string(1)
+    assert fc.fcfs_version() >= 100
+
+
+@pytest.mark.parametrize("args", [(0, 1, 0, 0), (1, 0, 0, 0), (3, 2, 9, 0), (3, 2, 0, 7), (-1, 2, 1, 1)])
+def test_plan_rejects_bad_arguments(args):
+    with pytest.raises(fc.FcfsError) as e:
+        fc.fcfs_plan(*args)
+    assert e.value.status == fc.E_INVAL
+
+
+def test_plan_rejects_large_factors():
+    with pytest.raises(fc.FcfsError) as e:
+        fc.fcfs_plan(33, 1, 1, 0)
+    assert e.value.status == fc.E_UNSUPPORTED
+    # reduces before checking: 66/64 = 33/32 is too large, 64/32 = 2/1 is fine
+    fc.fcfs_plan_destroy(fc.fcfs_plan(64, 32, 1, 0))
+
+
+def test_forward_validation_needs_no_gpu():
+    plan = fc.fcfs_plan(3, 2, 1, 1)
+    # null pointers, bad sizes, weight given to a fixed method, dtype out of range
+    assert fc.fcfs_forward(plan, 0, 1, 1, 8, 8, None, None, 1, None, None) == fc.E_INVAL
+    assert fc.fcfs_forward(plan, 0, -1, 1, 8, 8, 16, None, 1, 16, None) == fc.E_INVAL
+    # an empty problem is a valid no-op, whatever its pointers
+    assert fc.fcfs_forward(plan, 0, 0, 1, 8, 8, None, None, 1, None, None) == fc.OK
+    assert fc.fcfs_forward(plan, 0, 1, 1, 0, 8, None, None, 1, None, None) == fc.OK
+    assert fc.fcfs_forward(plan, 0, 1, 1, 8, 8, 16, 16, 1, 16, None) == fc.E_INVAL
+    assert fc.fcfs_forward(plan, 5, 1, 1, 8, 8, 16, None, 1, 16, None) == fc.E_INVAL
+    assert fc.fcfs_forward(plan, 0, 1, 2, 8, 8, 16, None, 3, 16, None) == fc.E_INVAL
+    # a plane of 2^31 output samples is refused before any launch
+    assert fc.fcfs_forward(plan, 0, 1, 1, 40000, 40000, 16, None, 1, 16, None) == fc.E_UNSUPPORTED
+    dw = fc.fcfs_plan(3, 2, 3, 1)
+    assert fc.fcfs_forward(dw, 0, 1, 1, 8, 8, 16, None, 1, 16, None) == fc.E_INVAL
+    fc.fcfs_plan_destroy(plan)
+    fc.fcfs_plan_destroy(dw)
+
+
+FRACS = [(1, 1), (3, 2), (2, 3), (5, 4), (4, 5), (3, 4), (1, 2), (2, 1), (7, 3), (6, 4), (2, 11),
+         (27, 11), (8, 1), (1, 8), (32, 31), (31, 32)]
+
+
+@pytest.mark.parametrize("p,q", FRACS)
+@pytest.mark.parametrize("method", ["nearest", "bilinear", "bicubic"])
+@pytest.mark.parametrize("grid", ["half", "paper", "asym"])
+def test_plan_tables_match_oracle_kernels(p, q, method, grid):
+    pl = fc.Plan(p, q, method, "zero", grid)
+    for j in range(pl.p_red):
+        off, w = fc.fcfs_plan_taps(pl.handle, 0, j)
+        h = oracle.phase_kernel(p, q, method, grid, j)
+        K = (len(h) - 1) // 2
+        dense = np.zeros_like(h)
+        for t in range(pl.taps):
+            o = off + t
+            assert -K <= o <= K
+            dense[K - o] += w[t]
+        # FP32 weights from FP64: one rounding
+        np.testing.assert_allclose(dense, h, rtol=0, atol=2e-7, err_msg=f"phase {j}")
+
+
+@pytest.mark.parametrize("p,q", FRACS)
+def test_output_size_matches_oracle(p, q):
+    pl = fc.Plan(p, q, "bilinear", "zero")
+    for n in (1, 2, 5, 7, 64, 67, 1023, 1024, 2048):
+        assert pl.output_size(n, n + 1) == (oracle.out_len(p, q, n), oracle.out_len(p, q, n + 1))
+
+
+def test_anisotropic_plan():
+    pl = fc.Plan(3, 2, "bicubic", "reflect", pw=5, qw=4)
+    assert pl.output_size(10, 16) == (15, 20)
+    # an axis at 1/1 next to a resampled one keeps the method's four taps
+    pl = fc.Plan(1, 1, "bicubic", "reflect", pw=3, qw=2)
+    assert pl.taps == 4
+    assert fc.fcfs_plan_taps(pl.handle, 0, 0)[1] == [0.0, 1.0, 0.0, 0.0]
