@@ -136,8 +136,9 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
 
 /* Launch geometry fcfs_forward would use for these sizes (introspection for
  * tests and benchmarks; enqueues nothing). kernel_id identifies the compiled
- * kernel instance: dtype*100 + taps*10 + column groups per lane (+ 1000 for
- * the learned depthwise layer, 2000 for the channel-mixing layer). Any
+ * kernel instance: dtype*1000 + taps*100 + column groups per lane*10 + staged
+ * row dwords per lane (+ 10000 for the learned depthwise layer, 20000 for the
+ * channel-mixing layer). Any
  * output pointer may be NULL. Errors: as fcfs_forward's argument checks. */
 fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
                                 int64_t h, int64_t w, int* kernel_id, int* strip_width,

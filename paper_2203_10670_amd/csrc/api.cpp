@@ -100,24 +100,28 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
       off = (int)b - 1;
       if (!learned) keys_taps(frac, w);
     }
-    t->off[j] = (int8_t)off;
+    t->off[j] = off;
     for (int k = 0; k < 4; ++k) t->w[j][k] = (float)w[k];
     omin = std::min(omin, off);
     omax = std::max(omax, off + T - 1);
   }
   t->omin = omin;
   t->omax = omax;
-  uint32_t mask = 0;
+  bool read[kMaxFactor] = {false};
   for (int j = 0; j < p; ++j)
-    for (int k = 0; k < T; ++k) mask |= 1u << mod_pos(t->off[j] + k, q);
-  t->need_mask = mask;
+    for (int k = 0; k < T; ++k) read[mod_pos(t->off[j] + k, q)] = true;
+  for (int r = 0; r < q; ++r) {
+    int d = 0;
+    while (!read[mod_pos(r - d, q)]) ++d;
+    t->back[r] = d;
+  }
   int n = 0;
   for (int r = 0; r < q; ++r) {
-    t->emit_start[r] = (uint8_t)n;
+    t->emit_start[r] = n;
     for (int j = 0; j < p; ++j)
-      if (mod_pos(t->off[j] + T - 1, q) == r) t->emit_list[n++] = (uint8_t)j;
+      if (mod_pos(t->off[j] + T - 1, q) == r) t->emit_list[n++] = j;
   }
-  t->emit_start[q] = (uint8_t)n;
+  t->emit_start[q] = n;
   return FCFS_OK;
 }
 
@@ -128,14 +132,16 @@ fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int
   const AxisTable& aw = plan->aw;
   const AxisTable& ah = plan->ah;
   const int span = aw.omax - aw.omin + 1;
-  const int cap = 512;   // staged row segment per wave (kRowDwords * 64)
+  // staged columns of a strip of tw outputs, at most (see the kernel)
   auto seg = [&](int tw) { return aw.q * ((tw + aw.p - 2) / aw.p) + span; };
   const bool learned = plan->method == FCFS_LEARNED_DW4;
   int kc = learned ? 1 : 4;
-  while (kc > 1 && (seg(64 * kc) > cap || wo <= 64 * (kc / 2))) kc /= 2;
+  while (kc > 1 && (seg(64 * kc) > 512 || wo <= 64 * (kc / 2))) kc /= 2;
   int tw = 64 * kc;
-  while (tw > 1 && seg(tw) > cap) tw /= 2;
-  if (seg(tw) > cap) return FCFS_E_UNSUPPORTED;
+  while (tw > 1 && seg(tw) > 512) tw /= 2;
+  if (seg(tw) > 512) return FCFS_E_UNSUPPORTED;
+  const int need = seg(tw);
+  g->slots = need <= 128 ? 2 : (need <= 256 ? 4 : 8);
   g->kc = kc;
   g->tw = tw;
   g->strips = (wo + tw - 1) / tw;
@@ -276,7 +282,12 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
   a.band_cells = g.band_cells;
   a.bands = g.bands;
   a.waves = g.waves;
-  return launch_forward_fixed(plan, dtype, a, g, stream);
+  if (g.waves <= 0) return FCFS_OK;
+  switch (dtype) {
+    case FCFS_F32: return launch_forward_f32(plan->method, a, g, stream);
+    case FCFS_BF16: return launch_forward_bf16(plan->method, a, g, stream);
+    default: return launch_forward_f16(plan->method, a, g, stream);
+  }
 }
 
 fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
@@ -292,9 +303,9 @@ fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
     st = plan_forward_geom(plan, n * c_in, (int)h, (int)w, (int)ho, (int)wo, &g);
     if (st != FCFS_OK) return st;
   }
-  int id = (int)dtype * 100 + plan->ah.T * 10 + g.kc;
-  if (plan->method == FCFS_LEARNED_DW4) id += 1000;
-  if (plan->method == FCFS_LEARNED_MIX4) id += 2000;
+  int id = (int)dtype * 1000 + plan->ah.T * 100 + g.kc * 10 + g.slots;
+  if (plan->method == FCFS_LEARNED_DW4) id += 10000;
+  if (plan->method == FCFS_LEARNED_MIX4) id += 20000;
   if (kernel_id) *kernel_id = id;
   if (strip_width) *strip_width = g.tw;
   if (band_cells) *band_cells = g.band_cells;

@@ -12,15 +12,16 @@ constexpr int kMaxFactor = 32;   // largest reduced p or q a plan accepts
 // Per-axis tap table of a plan (paper Sec. 3.1.1 and Sec. 5.2): output sample
 // k = p*m + j reads input samples q*m + off[j] + t, t = 0..T-1, with weights
 // w[j][t]. Passed to kernels by value (it lives in the kernel-argument
-// segment).
+// segment); every field is 4-byte aligned so uniform lookups are scalar loads.
 struct AxisTable {
   int p, q;                  // reduced factor
   int T;                     // taps: 1 nearest, 2 bilinear, 4 bicubic / learned
   int omin, omax;            // smallest first tap and largest last tap offset
-  uint32_t need_mask;        // bit r: some tap reads an input index = r (mod q)
-  int8_t off[kMaxFactor];    // first tap offset of each phase (in [-2, q])
-  uint8_t emit_start[kMaxFactor + 1];  // phases whose last tap is = r (mod q):
-  uint8_t emit_list[kMaxFactor];       //   emit_list[emit_start[r] .. emit_start[r+1])
+  int off[kMaxFactor];       // first tap offset of each phase (in [-2, q])
+  int emit_start[kMaxFactor + 1];  // phases whose last tap is = r (mod q) are
+  int emit_list[kMaxFactor];       //   emit_list[emit_start[r] .. emit_start[r+1])
+  int back[kMaxFactor];      // per residue r: distance down to the nearest row
+                             // index some tap reads (0 when taps read r itself)
   float w[kMaxFactor][4];    // tap weights (fixed methods; unused when learned)
 };
 
@@ -42,6 +43,7 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
 // Launch geometry of the fused forward kernel.
 struct FwdGeom {
   int kc;            // output-column groups per lane (1, 2 or 4)
+  int slots;         // staged row-segment dwords per lane (2, 4 or 8)
   int tw;            // output columns per wave strip
   int strips;        // strips per plane
   int band_cells;    // hidden-layer cells (row groups) per wave band
@@ -62,9 +64,10 @@ struct FwdArgs {
   AxisTable th, tw_tab;
 };
 
-// Kernel launchers (fwd.hip). dtype: fcfs_dtype.
-fcfs_status launch_forward_fixed(const fcfs_plan_* plan, int dtype, const FwdArgs& a,
-                                 const FwdGeom& g, hipStream_t stream);
+// Forward kernel launchers, one per storage type (fwd_<dtype>.hip).
+fcfs_status launch_forward_f32(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);
+fcfs_status launch_forward_bf16(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);
+fcfs_status launch_forward_f16(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);
 
 // Host-side launch geometry for a plane of (h, w) -> (ho, wo).
 fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho,

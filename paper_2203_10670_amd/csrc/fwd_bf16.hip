@@ -1,0 +1,10 @@
+// Instantiation of the fused forward kernels for BF16 storage.
+#include "fwd_kernel.h"
+
+namespace fcfs {
+
+fcfs_status launch_forward_bf16(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
+  return fwd::launch_forward_dt<FCFS_BF16>(method, a, g, stream);
+}
+
+}  // namespace fcfs

@@ -7,9 +7,10 @@
 // LDS row buffer, so a workgroup is just four independent waves.
 //
 // Per wave the kernel streams the input rows its band needs, top to bottom:
-//   1. the row segment the strip needs is prefetched D rows ahead into
-//      registers (coalesced loads, padding applied by remapping the source
-//      column; zero padding loads nothing),
+//   1. the row segment the strip needs is prefetched kPrefetch rows ahead
+//      into registers (coalesced dword loads; padding is applied by remapping
+//      the source row and column, zero padding by a select afterwards, so the
+//      loads themselves are unconditional and stay in flight),
 //   2. the row is staged in the wave's LDS buffer and every lane evaluates the
 //      horizontal taps of its output columns (the separable kernel's width
 //      pass), giving one value per column,
@@ -18,21 +19,23 @@
 //      from the FIFO with the phase's height taps and stored at its
 //      pixelshuffled position (output row p*m + j).
 // The hidden layer of the paper is never materialised and each output sample
-// is written exactly once. Rows no tap reads (nearest, large q) are skipped.
+// is written exactly once. Rows no tap reads (nearest, large q) are not
+// fetched: their slot re-reads the nearest row below that is (a cache hit).
 //
 // The learned depthwise variant keeps the T x T raw taps per column in the
 // FIFO instead (its 4x4 kernels are not separable) and reads the per-channel
 // weights of the phase from LDS.
+#pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "fcfs_internal.h"
 
 namespace fcfs {
-namespace {
+namespace fwd {
 
 constexpr int kWaves = 4;       // waves per workgroup
-constexpr int kRowDwords = 8;   // row-segment slots per lane (segment <= 512 samples)
+constexpr int kRowMax = 512;    // staged row segment per wave (floats)
 constexpr int kPrefetch = 4;    // rows in flight per wave
 
 // ---------------------------------------------------------------- storage types
@@ -45,11 +48,11 @@ template <> struct Store<FCFS_F32> {
 template <> struct Store<FCFS_BF16> {
   using T = uint16_t;
   static __device__ __forceinline__ float load(const T* p) {
-    uint32_t b = *p;
+    const uint32_t b = *p;
     return __uint_as_float(b << 16);
   }
   static __device__ __forceinline__ void store(T* p, float v) {
-    uint32_t u = __float_as_uint(v);
+    const uint32_t u = __float_as_uint(v);
     uint16_t r;
     if ((u & 0x7fffffffu) > 0x7f800000u) r = (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
     else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);               // round to nearest even
@@ -76,17 +79,20 @@ __device__ __forceinline__ int pad_source(int i, int n, int mode) {
 }
 
 __device__ __forceinline__ int mod_pos(int a, int q) {
-  int m = a % q;
+  const int m = a % q;
   return m < 0 ? m + q : m;
 }
 
+// Orders this wave's LDS writes before its later LDS reads and vice versa
+// (LDS operations of one wave execute in order; this keeps the compiler from
+// moving them across each other).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int DT, int T, int KC, bool LEARNED>
+template <int DT, int T, int KC, int L, bool LEARNED>
 __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   using S = Store<DT>;
   using TS = typename S::T;
@@ -111,21 +117,19 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   const int m1 = min(m0 + a.band_cells, a.Mh);
 
   const int n0 = ow0 / TW.p;
-  const int cs = TW.q * n0 + TW.omin;                      // first input column staged
-  const int nLast = (owEnd - 1) / TW.p;
-  const int CW = TW.q * (nLast - n0) + TW.omax - TW.omin + 1;  // staged columns
+  const int cs = TW.q * n0 + TW.omin;   // first input column staged
 
-  float* row = smem + wslot * (kRowDwords * 64);
+  float* row = smem + wslot * kRowMax;
   float* wl = nullptr;
-  const int nph = TH.p * TW.p;
   if constexpr (LEARNED) {
-    wl = smem + kWaves * (kRowDwords * 64) + wslot * (nph * 16);
+    const int nph = TH.p * TW.p;
+    wl = smem + kWaves * kRowMax + wslot * (nph * 16);
     const float* wsrc = a.weight + (int64_t)(plane % a.C) * nph * 16;
     for (int i = lane; i < nph * 16; i += 64) wl[i] = wsrc[i];
     wave_lds_sync();
   }
 
-  // Columns of this lane: ow0 + lane + 64*c.
+  // Output columns of this lane: ow0 + lane + 64*c.
   int pos[KC];
   int ocol[KC];
   int wbase[KC];
@@ -145,12 +149,15 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
     for (int b = 0; b < T; ++b) wc[c][b] = LEARNED ? 0.f : TW.w[jw][b];
   }
 
-  // Source column of each staged slot (lane + 64*s); -1 = zero.
-  int scol[kRowDwords];
+  // Source column of each staged slot lane + 64*s, clamped into the row;
+  // ckeep = false where zero padding supplies the value.
+  int scol[L];
+  bool ckeep[L];
 #pragma unroll
-  for (int s = 0; s < kRowDwords; ++s) {
-    const int i = lane + 64 * s;
-    scol[s] = (i < CW) ? pad_source(cs + i, a.W, a.pad) : -1;
+  for (int s = 0; s < L; ++s) {
+    const int src = pad_source(cs + lane + 64 * s, a.W, a.pad);
+    ckeep[s] = src >= 0;
+    scol[s] = src >= 0 ? src : 0;
   }
 
   const TS* xplane = reinterpret_cast<const TS*>(a.x) + plane * (int64_t)a.H * a.W;
@@ -159,22 +166,23 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   const int rs = TH.q * m0 + TH.omin;
   const int re = TH.q * (m1 - 1) + TH.omax;
 
-  auto row_needed = [&](int r) -> bool { return (TH.need_mask >> mod_pos(r, TH.q)) & 1u; };
+  // Input row fetched for band row r: r itself when some tap reads it, else
+  // the nearest such row below (already fetched); rows past the band end
+  // repeat its last row. Returns the source row, or -1 for a zero row.
+  auto fetch_row = [&](int r) -> int {
+    r = min(r, re);
+    r -= TH.back[mod_pos(r, TH.q)];
+    return pad_source(r, a.H, a.pad);
+  };
 
-  float buf[kPrefetch][kRowDwords];
-  auto load_row = [&](int r, float (&dst)[kRowDwords]) {
-    if (r > re || !row_needed(r)) return;
-    const int sr = pad_source(r, a.H, a.pad);
-    if (sr < 0) {
+  float buf[kPrefetch][L];
+  int bsrc[kPrefetch];
+  auto load_row = [&](int r, float (&dst)[L], int& src_out) {
+    const int sr = fetch_row(r);
+    src_out = sr;
+    const TS* src = xplane + (int64_t)(sr < 0 ? 0 : sr) * a.W;
 #pragma unroll
-      for (int s = 0; s < kRowDwords; ++s) dst[s] = 0.f;
-      return;
-    }
-    const TS* src = xplane + (int64_t)sr * a.W;
-#pragma unroll
-    for (int s = 0; s < kRowDwords; ++s) {
-      if (64 * s < CW) dst[s] = (scol[s] >= 0) ? S::load(src + scol[s]) : 0.f;
-    }
+    for (int s = 0; s < L; ++s) dst[s] = S::load(src + scol[s]);
   };
 
   // FIFO of the last T rows: fixed methods keep the width-filtered value per
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
       for (int b = 0; b < FT; ++b) fifo[c][t][b] = 0.f;
 
 #pragma unroll
-  for (int d = 0; d < kPrefetch; ++d) load_row(rs + d, buf[d]);
+  for (int d = 0; d < kPrefetch; ++d) load_row(rs + d, buf[d], bsrc[d]);
 
   int rho = mod_pos(rs, TH.q);
   for (int rb = rs; rb <= re; rb += kPrefetch) {
@@ -197,36 +205,28 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
     for (int d = 0; d < kPrefetch; ++d) {
       const int r = rb + d;
       if (r > re) break;
-      const bool need = (TH.need_mask >> rho) & 1u;
+      // stage the row (zero padding applied here), then refill the slot
+      const bool zrow = bsrc[d] < 0;
+#pragma unroll
+      for (int s = 0; s < L; ++s) row[lane + 64 * s] = (ckeep[s] && !zrow) ? buf[d][s] : 0.f;
+      load_row(r + kPrefetch, buf[d], bsrc[d]);
+      wave_lds_sync();
       float cur[KC][FT];
-      if (need) {
 #pragma unroll
-        for (int s = 0; s < kRowDwords; ++s)
-          if (64 * s < CW) row[lane + 64 * s] = buf[d][s];
-        load_row(r + kPrefetch, buf[d]);
-        wave_lds_sync();
+      for (int c = 0; c < KC; ++c) {
+        if constexpr (LEARNED) {
 #pragma unroll
-        for (int c = 0; c < KC; ++c) {
-          if constexpr (LEARNED) {
+          for (int b = 0; b < T; ++b) cur[c][b] = row[pos[c] + b];
+        } else if constexpr (T == 1) {
+          cur[c][0] = row[pos[c]];
+        } else {
+          float h = wc[c][0] * row[pos[c]];
 #pragma unroll
-            for (int b = 0; b < T; ++b) cur[c][b] = row[pos[c] + b];
-          } else if constexpr (T == 1) {
-            cur[c][0] = row[pos[c]];
-          } else {
-            float h = wc[c][0] * row[pos[c]];
-#pragma unroll
-            for (int b = 1; b < T; ++b) h = __builtin_fmaf(wc[c][b], row[pos[c] + b], h);
-            cur[c][0] = h;
-          }
+          for (int b = 1; b < T; ++b) h = __builtin_fmaf(wc[c][b], row[pos[c] + b], h);
+          cur[c][0] = h;
         }
-        wave_lds_sync();
-      } else {
-        load_row(r + kPrefetch, buf[d]);
-#pragma unroll
-        for (int c = 0; c < KC; ++c)
-#pragma unroll
-          for (int b = 0; b < FT; ++b) cur[c][b] = 0.f;
       }
+      wave_lds_sync();
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
 #pragma unroll
@@ -241,8 +241,7 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
       const int e1 = TH.emit_start[rho + 1];
       for (int e = TH.emit_start[rho]; e < e1; ++e) {
         const int j = TH.emit_list[e];
-        const int last = TH.off[j] + T - 1;
-        const int m = (r - last) / TH.q;   // exact: r = last (mod q)
+        const int m = (r - (TH.off[j] + T - 1)) / TH.q;   // exact: r = last tap (mod q)
         if (m < m0 || m >= m1) continue;
         TS* orow = yplane + (int64_t)(TH.p * m + j) * a.Wo;
         if constexpr (LEARNED) {
@@ -279,41 +278,38 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   }
 }
 
-template <int DT, int T, bool LEARNED>
-fcfs_status launch_kc(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
+template <int DT, int T, int KC, bool LEARNED>
+fcfs_status launch_l(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
   const dim3 block(64 * kWaves);
   const dim3 grid((unsigned)((g.waves + kWaves - 1) / kWaves));
-  size_t lds = sizeof(float) * kWaves * kRowDwords * 64;
+  size_t lds = sizeof(float) * kWaves * kRowMax;
   if (LEARNED) lds += sizeof(float) * kWaves * a.th.p * a.tw_tab.p * 16;
-  switch (g.kc) {
-    case 4: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, 4, LEARNED>), grid, block, lds, stream, a); break;
-    case 2: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, 2, LEARNED>), grid, block, lds, stream, a); break;
-    default: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, 1, LEARNED>), grid, block, lds, stream, a); break;
+  switch (g.slots) {
+    case 2: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED>), grid, block, lds, stream, a); break;
+    case 4: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 8, LEARNED>), grid, block, lds, stream, a); break;
   }
   return hipGetLastError() == hipSuccess ? FCFS_OK : FCFS_E_DEVICE;
 }
 
+template <int DT, int T>
+fcfs_status launch_kc(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
+  switch (g.kc) {
+    case 4: return launch_l<DT, T, 4, false>(a, g, stream);
+    case 2: return launch_l<DT, T, 2, false>(a, g, stream);
+    default: return launch_l<DT, T, 1, false>(a, g, stream);
+  }
+}
+
 template <int DT>
-fcfs_status launch_dt(const fcfs_plan_* plan, const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
-  if (plan->method == FCFS_LEARNED_DW4) return launch_kc<DT, 4, true>(a, g, stream);
-  switch (plan->ah.T) {
-    case 1: return launch_kc<DT, 1, false>(a, g, stream);
-    case 2: return launch_kc<DT, 2, false>(a, g, stream);
-    default: return launch_kc<DT, 4, false>(a, g, stream);
+fcfs_status launch_forward_dt(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
+  if (method == FCFS_LEARNED_DW4) return launch_l<DT, 4, 1, true>(a, g, stream);
+  switch (a.th.T) {
+    case 1: return launch_kc<DT, 1>(a, g, stream);
+    case 2: return launch_kc<DT, 2>(a, g, stream);
+    default: return launch_kc<DT, 4>(a, g, stream);
   }
 }
 
-}  // namespace
-
-fcfs_status launch_forward_fixed(const fcfs_plan_* plan, int dtype, const FwdArgs& a,
-                                 const FwdGeom& g, hipStream_t stream) {
-  if (g.waves <= 0) return FCFS_OK;
-  switch (dtype) {
-    case FCFS_F32: return launch_dt<FCFS_F32>(plan, a, g, stream);
-    case FCFS_BF16: return launch_dt<FCFS_BF16>(plan, a, g, stream);
-    case FCFS_F16: return launch_dt<FCFS_F16>(plan, a, g, stream);
-    default: return FCFS_E_INVAL;
-  }
-}
-
+}  // namespace fwd
 }  // namespace fcfs

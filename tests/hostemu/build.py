@@ -1,0 +1,45 @@
+"""Build libfcfs's kernels and host code for the CPU under the host emulation
+(test infrastructure; see hip/hip_runtime.h), with the address sanitizer."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2203_10670_amd", "csrc")
+OUT = os.path.join(HERE, "_build", "libfcfs_hostemu.so")
+SOURCES = ["api.cpp", "fwd_f32.hip", "fwd_bf16.hip", "fwd_f16.hip"]
+
+
+def build(sanitize: bool = True) -> str:
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES] + [os.path.join(HERE, "emu_main.cpp")]
+    newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(HERE, "hip", "hip_runtime.h")])
+    if os.path.exists(OUT) and os.path.getmtime(OUT) >= newest:
+        return OUT
+    flags = ["-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-w",
+             "-I", HERE, "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    if sanitize:
+        flags += ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(os.path.dirname(OUT), "obj")
+    os.makedirs(objdir, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        subprocess.check_call(["g++"] + [f for f in flags if f != "-shared"] + ["-c", "-x", "c++", src, "-o", obj])
+        return obj
+
+    with ThreadPoolExecutor(max(1, min(len(srcs), os.cpu_count() or 2))) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    tmp = OUT + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++"] + flags + objs + ["-o", tmp])
+    os.replace(tmp, OUT)
+    return OUT
+
+
+def asan_runtime() -> str:
+    return subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+
+
+if __name__ == "__main__":
+    print(build())

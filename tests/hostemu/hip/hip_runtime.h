@@ -1,0 +1,109 @@
+// Host emulation of the HIP device-side dialect used by libfcfs kernels (see
+// hip_runtime_api.h). Workgroups run one after another; the lanes of a
+// workgroup are std::threads; __builtin_amdgcn_wave_barrier is a barrier over
+// the 64 lanes of the wave; LDS is one static array shared by the workgroup.
+#pragma once
+#include <algorithm>
+#include <barrier>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "hip_runtime_api.h"
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+namespace hostemu {
+inline thread_local dim3 tid_, bid_;
+inline thread_local std::barrier<>* wave_bar_ = nullptr;
+constexpr size_t kLdsFloats = 160 * 1024 / 4;
+}  // namespace hostemu
+
+// The dynamic LDS arrays: every kernel declares `extern __shared__ float
+// smem[]` at block scope, which names an array of its own namespace; the
+// emulation main file defines one per kernel namespace and lists them here.
+namespace hostemu {
+extern float* const lds_arrays[];
+extern const int n_lds_arrays;
+}  // namespace hostemu
+
+#define threadIdx (hostemu::tid_)
+#define blockIdx (hostemu::bid_)
+
+template <class T> inline T min(T a, T b) { return a < b ? a : b; }
+template <class T> inline T max(T a, T b) { return a > b ? a : b; }
+inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
+inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
+#define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_fence(...) ((void)0)
+#define __builtin_amdgcn_wave_barrier() (hostemu::wave_bar_->arrive_and_wait())
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))
+#define __builtin_nontemporal_load(p) (*(p))
+
+// IEEE binary16 storage with round-to-nearest-even conversion from float.
+struct _Float16 {
+  uint16_t bits;
+  _Float16() = default;
+  explicit _Float16(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t sign = (u >> 16) & 0x8000u;
+    uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) { bits = (uint16_t)(sign | 0x7e00u); return; }
+    if (a >= 0x477ff000u) { bits = (uint16_t)(sign | 0x7c00u); return; }   // rounds to inf
+    if (a < 0x38800000u) {                                               // subnormal or zero
+      float m = __uint_as_float(a) * 16777216.0f;                        // * 2^24, exact
+      bits = (uint16_t)(sign | (uint32_t)std::nearbyint(m));
+      return;
+    }
+    uint32_t mant = a & 0x7fffffu, exp = (a >> 23) - 112;
+    uint32_t h = (exp << 10) | (mant >> 13);
+    uint32_t rest = mant & 0x1fffu;
+    if (rest > 0x1000u || (rest == 0x1000u && (h & 1u))) ++h;
+    bits = (uint16_t)(sign | h);
+  }
+  operator float() const {
+    uint32_t sign = (uint32_t)(bits & 0x8000u) << 16;
+    uint32_t e = (bits >> 10) & 0x1f, m = bits & 0x3ffu;
+    if (e == 0) return (sign ? -1.f : 1.f) * (float)m / 16777216.0f;
+    if (e == 31) return __uint_as_float(sign | 0x7f800000u | (m << 13));
+    return __uint_as_float(sign | ((e + 112) << 23) | (m << 13));
+  }
+};
+
+template <class K, class... A>
+inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... args) {
+  if (lds > hostemu::kLdsFloats * 4) std::abort();
+  const unsigned nthreads = block.x, nwaves = (nthreads + 63) / 64;
+  for (unsigned b = 0; b < grid.x; ++b) {
+    std::vector<std::unique_ptr<std::barrier<>>> bars;
+    for (unsigned w = 0; w < nwaves; ++w) bars.emplace_back(new std::barrier<>(64));
+    for (int i = 0; i < hostemu::n_lds_arrays; ++i)   // stale LDS reads as NaN
+      std::memset(hostemu::lds_arrays[i], 0xff, lds);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nthreads; ++t)
+      th.emplace_back([=, &bars] {
+        hostemu::tid_ = dim3(t);
+        hostemu::bid_ = dim3(b);
+        hostemu::wave_bar_ = bars[t / 64].get();
+        kernel(args...);
+        // lanes of a wave that returned early no longer take part in barriers
+        hostemu::wave_bar_->arrive_and_drop();
+      });
+    for (auto& x : th) x.join();
+  }
+}
+#define hipLaunchKernelGGL(k, grid, block, lds, stream, ...) hostemu_launch(k, grid, block, lds, __VA_ARGS__)

@@ -1,0 +1,85 @@
+"""Runs forward cases through the host-emulated libfcfs (CPU, sanitizers on)
+and compares them with the FP64 oracle. Invoked by the test in a subprocess
+with the address-sanitizer runtime preloaded. Prints one line per case and
+exits non-zero on the first mismatch."""
+import ctypes
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+METHODS = {"nearest": 0, "bilinear": 1, "bicubic": 2, "dw4": 3}
+PADS = {"zero": 0, "replicate": 1, "reflect": 2}
+GRIDS = {"half": 0, "paper": 1, "asym": 2}
+DT = {"f32": 0, "bf16": 1, "f16": 2}
+UNIT = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+
+
+def to_storage(x, dt):
+    if dt == "f32":
+        return np.ascontiguousarray(x, np.float32), np.ascontiguousarray(x, np.float32)
+    if dt == "f16":
+        h = np.ascontiguousarray(x, np.float32).astype(np.float16)
+        return h, h.astype(np.float32)
+    r = synth.bf16_round(x)
+    bits = (r.view(np.uint32) >> 16).astype(np.uint16)
+    return bits, r
+
+
+def from_storage(y, dt):
+    if dt == "bf16":
+        return (y.astype(np.uint32) << 16).view(np.float32)
+    return y.astype(np.float32)
+
+
+def main():
+    lib = ctypes.CDLL(sys.argv[1])
+    cases = json.loads(sys.argv[2])
+    P = ctypes.c_void_p
+    lib.fcfs_plan_ex.argtypes = [ctypes.c_int] * 7 + [ctypes.POINTER(P)]
+    lib.fcfs_forward.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 4 + [P, P, ctypes.c_int64, P, P]
+    lib.fcfs_output_size.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    for i, c in enumerate(cases):
+        p, q, pw, qw = c["p"], c["q"], c.get("pw", c["p"]), c.get("qw", c["q"])
+        N, C, H, W = c["shape"]
+        m, pad, grid, dt = c["method"], c["pad"], c.get("grid", "half"), c.get("dtype", "f32")
+        plan = P()
+        assert lib.fcfs_plan_ex(p, q, pw, qw, METHODS[m], PADS[pad], GRIDS[grid], ctypes.byref(plan)) == 0
+        ho, wo = ctypes.c_int64(), ctypes.c_int64()
+        lib.fcfs_output_size(plan, H, W, ctypes.byref(ho), ctypes.byref(wo))
+        x = synth.normal(1000 + i, (N, C, H, W))
+        xs, xv = to_storage(x, dt)
+        w = None
+        if m == "dw4":
+            from math import gcd
+            w = synth.normal(2000 + i, (C, p // gcd(p, q), pw // gcd(pw, qw), 4, 4)).astype(np.float32)
+        y = np.zeros((N, C, ho.value, wo.value), dtype=xs.dtype)
+        st = lib.fcfs_forward(plan, DT[dt], N, C, H, W, xs.ctypes.data, None if w is None else w.ctypes.data,
+                              C, y.ctypes.data, None)
+        assert st == 0, st
+        yv = from_storage(y, dt).astype(np.float64)
+        r = oracle.forward(xv.astype(np.float64), p, q, m, pad, grid, weight=w, pw=pw, qw=qw)
+        if m == "nearest":
+            ok = np.array_equal(yv, r)
+        else:
+            S = oracle.condition(xv, p, q, m, pad, grid, weight=w, pw=pw, qw=qw)
+            ok = bool((np.abs(yv - r) <= UNIT[dt] * np.abs(r) + 1e-5 * S + 1e-30).all())
+        print("case", i, json.dumps(c), "ok" if ok else "MISMATCH", flush=True)
+        if not ok:
+            bad = np.argwhere(np.abs(yv - r) > 1e-5 * np.abs(r) + 1e-6)
+            print("first bad", bad[:5].tolist(), yv[tuple(bad[0])], r[tuple(bad[0])], flush=True)
+            sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()
