@@ -99,6 +99,39 @@ def cpu_baseline(cases, x_np, target_planes: int):
                       "(%.1f s wall)" % (k, SHAPE[0] * SHAPE[1], len(cases), dt)}
 
 
+def summarize(d):
+    """Per-kernel summary of rocprofv3 CSV output (kernel stats, and FETCH_SIZE /
+    WRITE_SIZE counters per dispatch when present), printed as text."""
+    import csv
+    import glob
+    stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    for f in stats:
+        print("# kernel stats:", os.path.relpath(f, d))
+        with open(f) as fh:
+            rows = list(csv.DictReader(fh))
+        rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+        print("%-60s %6s %12s %12s %6s" % ("kernel", "calls", "avg_us", "total_us", "pct"))
+        for r in rows:
+            name = r["Name"]
+            short = name if len(name) <= 60 else name[:57] + "..."
+            print("%-60s %6s %12.2f %12.1f %6.2f" % (short, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                      float(r["TotalDurationNs"]) / 1e3, float(r["Percentage"])))
+    ctr = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    for f in ctr:
+        print("# counters:", os.path.relpath(f, d))
+        agg = {}
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                key = (r["Kernel_Name"], r["Counter_Name"])
+                a = agg.setdefault(key, [0.0, 0])
+                a[0] += float(r["Counter_Value"])
+                a[1] += 1
+        print("%-60s %-12s %8s %16s" % ("kernel", "counter", "rows", "avg_KiB_per_row"))
+        for (k, c), (v, n) in sorted(agg.items()):
+            short = k if len(k) <= 60 else k[:57] + "..."
+            print("%-60s %-12s %8d %16.1f" % (short, c, n, v / n))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +140,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=0)
+    ap.add_argument("--filter", default="", help="only cases whose name contains this text")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 CSV output under DIR and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the rescale path has no multi-GPU mode "
               "(run with --gpus 1)", file=sys.stderr)
@@ -173,7 +213,25 @@ def main():
             out.append((cs, us))
         return out
 
+    if args.copy_calibration:
+        n = 1 << 28   # 1 GiB of FP32 read and written
+        a_ = torch.rand(n, device=dev)
+        b_ = torch.empty_like(a_)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            b_.copy_(a_)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        print("copy 1 GiB: %.3f ms, %.1f GB/s (read + write)" % (ms, 2 * 4 * n / (ms * 1e-3) / 1e9),
+              file=sys.stderr, flush=True)
+        del a_, b_
+
     f32 = make_cases("f32", x32, 4)
+    if args.filter:
+        f32 = [c for c in f32 if args.filter in "%d/%d %s %s" % (c["p"], c["q"], c["method"], c["pad"])]
     ms_step = timed_sweep(f32, args.steps, args.warmup)
     step_bytes = sum(c["bytes"] for c in f32)
     value = step_bytes / (ms_step * 1e-3) / 1e9
@@ -201,7 +259,7 @@ def main():
                           "us": round(us, 2), "GBps": round(c["bytes"] / (us * 1e-6) / 1e9, 1),
                           "kernel_id": c["kernel_id"]} for c, us in pc]}
     bf16_value = None
-    if not args.no_bf16:
+    if not args.no_bf16 and not args.filter:
         del pc
         bf = make_cases("bf16", xbf, 2)
         ms_bf = timed_sweep(bf, args.steps, args.warmup)
@@ -216,7 +274,7 @@ def main():
     torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.filter:
         cpu = cpu_baseline(f32, x_np, args.cpu_planes)
 
     line = {

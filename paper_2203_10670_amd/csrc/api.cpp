@@ -135,7 +135,10 @@ fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int
   // staged columns of a strip of tw outputs, at most (see the kernel)
   auto seg = [&](int tw) { return aw.q * ((tw + aw.p - 2) / aw.p) + span; };
   const bool learned = plan->method == FCFS_LEARNED_DW4;
-  int kc = learned ? 1 : 4;
+#ifndef FCFS_FWD_MAX_KC
+#define FCFS_FWD_MAX_KC 4
+#endif
+  int kc = learned ? 1 : FCFS_FWD_MAX_KC;
   while (kc > 1 && (seg(64 * kc) > 512 || wo <= 64 * (kc / 2))) kc /= 2;
   int tw = 64 * kc;
   while (tw > 1 && seg(tw) > 512) tw /= 2;
@@ -146,14 +149,27 @@ fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int
   g->tw = tw;
   g->strips = (wo + tw - 1) / tw;
   const int Mh = ho / ah.p;
-  // Enough waves to fill 256 CUs several times over; bands of at least two cells.
-  const int64_t target_waves = 16384;
-  const int64_t per_band = planes * g->strips;
-  int64_t bands = (target_waves + per_band - 1) / per_band;
-  bands = std::max<int64_t>(1, std::min<int64_t>(bands, std::max(1, Mh / 2)));
-  int band_cells = (int)((Mh + bands - 1) / bands);
-  g->band_cells = band_cells;
-  g->bands = (Mh + band_cells - 1) / band_cells;
+  // Bands of cells. Consecutive waves take the strips of one band, then the
+  // next band of the same plane, so the waves in flight together work on
+  // nearby rows of few planes. A band of c cells streams q*(c-1) + span input
+  // rows; bands are sized to about FCFS_FWD_BAND_ROWS rows: small enough for
+  // many waves (latency hiding, a short tail at the end of the launch), large
+  // enough that the span - q rows re-read above each band stay a modest share.
+#ifndef FCFS_FWD_BAND_ROWS_T1
+#define FCFS_FWD_BAND_ROWS_T1 4
+#endif
+#ifndef FCFS_FWD_BAND_ROWS_T2
+#define FCFS_FWD_BAND_ROWS_T2 12
+#endif
+#ifndef FCFS_FWD_BAND_ROWS_T4
+#define FCFS_FWD_BAND_ROWS_T4 16
+#endif
+  const int span_h = ah.omax - ah.omin + 1;
+  const int rows = ah.T == 1 ? FCFS_FWD_BAND_ROWS_T1 : (ah.T == 2 ? FCFS_FWD_BAND_ROWS_T2 : FCFS_FWD_BAND_ROWS_T4);
+  // ... and at least four output rows per wave
+  const int cells = std::max({1, (rows - span_h) / ah.q + 1, (4 + ah.p - 1) / ah.p});
+  g->band_cells = cells;
+  g->bands = (Mh + cells - 1) / cells;
   g->waves = planes * g->strips * (int64_t)g->bands;
   return FCFS_OK;
 }

@@ -46,7 +46,7 @@ struct FwdGeom {
   int slots;         // staged row-segment dwords per lane (2, 4 or 8)
   int tw;            // output columns per wave strip
   int strips;        // strips per plane
-  int band_cells;    // hidden-layer cells (row groups) per wave band
+  int band_cells;    // hidden-layer cells (groups of p output rows) per band
   int bands;         // bands per plane
   int64_t waves;     // total waves
 };

@@ -2,9 +2,10 @@
 // convolution + pixelshuffle in one pass (paper Sec. 3.1 / Sec. 4.2).
 //
 // Work decomposition. One wave (64 lanes) owns a strip of `tw` output columns
-// of one (n, c) plane and a band of hidden-layer cells (`band_cells` groups of
-// p output rows). Waves never synchronise with each other: each has a private
-// LDS row buffer, so a workgroup is just four independent waves.
+// of one (n, c) plane and a band of `band_cells` hidden-layer cells (groups
+// of p output rows). Waves never synchronise with
+// each other: each has a private LDS row buffer, so a workgroup is just four
+// independent waves.
 //
 // Per wave the kernel streams the input rows its band needs, top to bottom:
 //   1. the row segment the strip needs is prefetched kPrefetch rows ahead
@@ -34,16 +35,30 @@
 namespace fcfs {
 namespace fwd {
 
+#ifndef FCFS_FWD_PREFETCH
+#define FCFS_FWD_PREFETCH 4
+#endif
+#ifndef FCFS_FWD_XCD_SWIZZLE
+#define FCFS_FWD_XCD_SWIZZLE 0
+#endif
+#ifndef FCFS_FWD_NT_STORE
+#define FCFS_FWD_NT_STORE 1
+#endif
+
 constexpr int kWaves = 4;       // waves per workgroup
 constexpr int kRowMax = 512;    // staged row segment per wave (floats)
-constexpr int kPrefetch = 4;    // rows in flight per wave
+constexpr int kPrefetch = FCFS_FWD_PREFETCH;   // rows in flight per wave
+constexpr int kXcds = 8;        // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // ---------------------------------------------------------------- storage types
 template <int DT> struct Store;
 template <> struct Store<FCFS_F32> {
   using T = float;
   static __device__ __forceinline__ float load(const T* p) { return *p; }
-  static __device__ __forceinline__ void store(T* p, float v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ void store(T* p, float v) {
+    if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
+  }
 };
 template <> struct Store<FCFS_BF16> {
   using T = uint16_t;
@@ -56,13 +71,17 @@ template <> struct Store<FCFS_BF16> {
     uint16_t r;
     if ((u & 0x7fffffffu) > 0x7f800000u) r = (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
     else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);               // round to nearest even
-    __builtin_nontemporal_store(r, p);
+    if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store(r, p);
+    else *p = r;
   }
 };
 template <> struct Store<FCFS_F16> {
   using T = _Float16;
   static __device__ __forceinline__ float load(const T* p) { return (float)*p; }
-  static __device__ __forceinline__ void store(T* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
+  static __device__ __forceinline__ void store(T* p, float v) {
+    if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store((_Float16)v, p);
+    else *p = (_Float16)v;
+  }
 };
 
 // Source index of position i of an axis of length n under the padding mode,
@@ -100,7 +119,17 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
 
   const int lane = threadIdx.x & 63;
   const int wslot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t wid = (int64_t)blockIdx.x * kWaves + wslot;
+  int64_t blk = blockIdx.x;
+  if (FCFS_FWD_XCD_SWIZZLE) {
+    // Workgroup b runs on XCD b % 8. Give each XCD a contiguous range of the
+    // logical order, so that neighbouring strips and bands (which share
+    // halo cache lines) meet in the same L2.
+    const int64_t nb = gridDim.x;
+    const int64_t per = nb / kXcds, rem = nb % kXcds;
+    const int64_t x = blk % kXcds, i = blk / kXcds;
+    blk = x * per + min(x, rem) + i;
+  }
+  const int64_t wid = blk * kWaves + wslot;
   if (wid >= a.waves) return;
 
   const AxisTable& TH = a.th;

@@ -28,7 +28,7 @@ struct dim3 {
 };
 
 namespace hostemu {
-inline thread_local dim3 tid_, bid_;
+inline thread_local dim3 tid_, bid_, grid_;
 inline thread_local std::barrier<>* wave_bar_ = nullptr;
 constexpr size_t kLdsFloats = 160 * 1024 / 4;
 }  // namespace hostemu
@@ -43,6 +43,7 @@ extern const int n_lds_arrays;
 
 #define threadIdx (hostemu::tid_)
 #define blockIdx (hostemu::bid_)
+#define gridDim (hostemu::grid_)
 
 template <class T> inline T min(T a, T b) { return a < b ? a : b; }
 template <class T> inline T max(T a, T b) { return a > b ? a : b; }
@@ -98,6 +99,7 @@ inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... arg
       th.emplace_back([=, &bars] {
         hostemu::tid_ = dim3(t);
         hostemu::bid_ = dim3(b);
+        hostemu::grid_ = grid;
         hostemu::wave_bar_ = bars[t / 64].get();
         kernel(args...);
         // lanes of a wave that returned early no longer take part in barriers
