@@ -63,6 +63,8 @@ def _load():
             lib.fcfs_oracle_forward_absw.restype = I
             lib.fcfs_oracle_backward.argtypes = [L, L, L, L, I, I, I, L, L, L, L, P, P, L, P, P, P]
             lib.fcfs_oracle_backward.restype = I
+            lib.fcfs_oracle_backward_absw.argtypes = lib.fcfs_oracle_backward.argtypes
+            lib.fcfs_oracle_backward_absw.restype = I
             lib.fcfs_oracle_threads.argtypes = []
             lib.fcfs_oracle_threads.restype = I
             _lib = lib
@@ -135,8 +137,9 @@ def condition(x, p, q, method="bilinear", pad="replicate", grid="half", weight=N
 
 
 def backward(dy, x_shape, p, q, method="bilinear", pad="replicate", grid="half", x=None,
-             weight=None, need_dx=True, need_dw=False, pw=None, qw=None):
-    """Adjoint of ``forward``: returns (dx or None, dw or None) in FP64."""
+             weight=None, need_dx=True, need_dw=False, pw=None, qw=None, abs_weights=False):
+    """Adjoint of ``forward``: returns (dx or None, dw or None) in FP64.
+    ``abs_weights``: use |w| for every tap (see ``condition_backward``)."""
     dy = _f64(dy)
     N, C, H, W = x_shape
     ph, qh, pw_, qw_ = _axes(p, q, pw, qw)
@@ -146,11 +149,23 @@ def backward(dy, x_shape, p, q, method="bilinear", pad="replicate", grid="half",
     w = _f64(weight)
     dw = np.empty_like(w) if need_dw else None
     xx = _f64(x)
-    rc = _load().fcfs_oracle_backward(ph, qh, pw_, qw_, m, PADS[pad], GRIDS[grid], N, C, H, W,
-                                      _ptr(xx), _ptr(w), co, _ptr(dy), _ptr(dx), _ptr(dw))
+    fn = _load().fcfs_oracle_backward_absw if abs_weights else _load().fcfs_oracle_backward
+    rc = fn(ph, qh, pw_, qw_, m, PADS[pad], GRIDS[grid], N, C, H, W,
+            _ptr(xx), _ptr(w), co, _ptr(dy), _ptr(dx), _ptr(dw))
     if rc != 0:
         raise ValueError("oracle backward rejected its arguments")
     return dx, dw
+
+
+def condition_backward(dy, x_shape, p, q, method="bilinear", pad="replicate", grid="half", x=None,
+                       weight=None, need_dw=False, pw=None, qw=None):
+    """Per-element scales of the gradients' rounding errors: the input
+    gradient's sum over taps of |w| |dy|, and the weight gradient's sum of
+    |dy| |x| (returned as (S_dx, S_dw))."""
+    ady = np.abs(np.asarray(dy, dtype=np.float64))
+    ax = None if x is None else np.abs(np.asarray(x, dtype=np.float64))
+    return backward(ady, x_shape, p, q, method, pad, grid, ax, weight, True, need_dw, pw, qw,
+                    abs_weights=True)
 
 
 def threads() -> int:

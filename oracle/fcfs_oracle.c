@@ -326,10 +326,10 @@ int fcfs_oracle_forward_absw(long rh, long sh, long rw, long sw, int method, int
  * dy: [N][Cout][Ho][Wo]. dx (nullable): [N][Cin][H][W]. dw (nullable, dw4/mix4
  * only): same layout as weight. x is needed only for dw.
  */
-int fcfs_oracle_backward(long rh, long sh, long rw, long sw, int method, int pad, int grid,
-                         long N, long Cin, long H, long W, const double* x,
-                         const double* weight, long Cout, const double* dy,
-                         double* dx, double* dw) {
+static int o_backward(long rh, long sh, long rw, long sw, int method, int pad, int grid,
+                      long N, long Cin, long H, long W, const double* x,
+                      const double* weight, long Cout, const double* dy,
+                      double* dx, double* dw, int absw) {
   o_geom g;
   if (o_geom_init(&g, rh, sh, rw, sw, H, W)) return -1;
   if (method < 0 || method > OM_MIX4 || pad < 0 || pad > OP_REFLECT || grid < 0 || grid > OG_ASYM) return -1;
@@ -338,7 +338,7 @@ int fcfs_oracle_backward(long rh, long sh, long rw, long sw, int method, int pad
   if (learned && !weight) return -1;
   if (dw && (!learned || !x)) return -1;
   long ngroups;
-  double* ker = o_build_kernels(&g, method, grid, weight, Cin, Cout, &ngroups, 0);
+  double* ker = o_build_kernels(&g, method, grid, weight, Cin, Cout, &ngroups, absw);
   if (!ker) return -1;
   long KH = 2 * g.Kh + 1, KW = 2 * g.Kw + 1, KHW = KH * KW;
   long plane_in = H * W, plane_p = g.Hp * g.Wp, cells = g.Mh * g.Mw;
@@ -456,6 +456,22 @@ int fcfs_oracle_backward(long rh, long sh, long rw, long sw, int method, int pad
 done:
   free(ker); free(dhid);
   return rc;
+}
+
+int fcfs_oracle_backward(long rh, long sh, long rw, long sw, int method, int pad, int grid,
+                         long N, long Cin, long H, long W, const double* x,
+                         const double* weight, long Cout, const double* dy,
+                         double* dx, double* dw) {
+  return o_backward(rh, sh, rw, sw, method, pad, grid, N, Cin, H, W, x, weight, Cout, dy, dx, dw, 0);
+}
+
+/* Conditioning of the input gradient for error bounds: the adjoint with every
+ * kernel tap replaced by its absolute value (apply it to |dy|). */
+int fcfs_oracle_backward_absw(long rh, long sh, long rw, long sw, int method, int pad, int grid,
+                              long N, long Cin, long H, long W, const double* x,
+                              const double* weight, long Cout, const double* dy,
+                              double* dx, double* dw) {
+  return o_backward(rh, sh, rw, sw, method, pad, grid, N, Cin, H, W, x, weight, Cout, dy, dx, dw, 1);
 }
 
 /* Number of OpenMP threads a parallel region uses (for reporting). */

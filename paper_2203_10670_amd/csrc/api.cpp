@@ -174,6 +174,76 @@ fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int
   return FCFS_OK;
 }
 
+
+// Upper bound of the adjoint-table entries of any input index of an axis of
+// length n with `cells` hidden cells: (most (phase, tap) pairs that read one
+// extended position) x (most extended positions the padding maps onto one
+// input index).
+static int adjoint_cmax(const AxisTable& t, int n, int cells, int pad) {
+  int per_pos = 0;
+  for (int r = 0; r < t.q; ++r) {
+    int c = 0;
+    for (int j = 0; j < t.p; ++j)
+      for (int k = 0; k < t.T; ++k)
+        if (mod_pos(t.off[j] + k - r, t.q) == 0) ++c;
+    per_pos = std::max(per_pos, c);
+  }
+  const int64_t emax = (int64_t)t.q * (cells - 1) + t.omax;
+  int64_t outside = std::max<int64_t>(0, -(int64_t)t.omin) + std::max<int64_t>(0, emax - n + 1);
+  int64_t positions = pad == FCFS_PAD_ZERO ? 1 : 1 + outside;
+  return (int)std::min<int64_t>((int64_t)per_pos * positions, 1 << 20);
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Fills the size-dependent fields of the backward arguments and returns the
+// workspace layout: [height table][width table][weight-gradient partials].
+static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, int h, int w, int ho,
+                                 int wo, bool need_dw, BwdArgs* a, size_t* ws_bytes, size_t* off_w,
+                                 size_t* off_p) {
+  a->planes = n * c;
+  a->C = (int)c;
+  a->H = h;
+  a->W = w;
+  a->Ho = ho;
+  a->Wo = wo;
+  a->Mh = ho / plan->ah.p;
+  a->Mw = wo / plan->aw.p;
+  a->pad = plan->pad;
+  a->th = plan->ah;
+  a->tw_tab = plan->aw;
+  a->col_blocks = (w + 255) / 256;
+  a->cmax_h = adjoint_cmax(plan->ah, h, a->Mh, plan->pad);
+  a->cmax_w = adjoint_cmax(plan->aw, w, a->Mw, plan->pad);
+  size_t bytes = align256(sizeof(int) * (size_t)h * (3 + a->cmax_h));
+  *off_w = bytes;
+  bytes += align256(sizeof(int) * (size_t)w * (3 + a->cmax_w));
+  *off_p = bytes;
+  if (need_dw) {
+    // chunks of ch x cw cells: staged x patch within 8192 floats
+    const AxisTable &th = plan->ah, &tw = plan->aw;
+    const int P2 = th.p * tw.p;
+    int side = 16;
+    auto lds_floats = [&](int ch, int cw) {
+      const int xr = th.q * (ch - 1) + th.omax - th.omin + 1, xc = tw.q * (cw - 1) + tw.omax - tw.omin + 1;
+      return th.p * ch * tw.p * cw + xr * xc + (256 / P2) * P2 * 16;
+    };
+    while (side > 1 && lds_floats(side, side) > 14336) --side;
+    a->ch = std::min(side, a->Mh);
+    a->cw = std::min(side, a->Mw);
+    a->nch = (a->Mh + a->ch - 1) / a->ch;
+    a->ncw = (a->Mw + a->cw - 1) / a->cw;
+    int64_t cpc = n * (int64_t)a->nch * a->ncw;
+    if (cpc > (1 << 30)) return FCFS_E_UNSUPPORTED;
+    a->chunks_per_channel = (int)cpc;
+    a->dw_lds_bytes = (int)(sizeof(float) * lds_floats(a->ch, a->cw));
+    if (a->dw_lds_bytes > 65536) return FCFS_E_UNSUPPORTED;
+    bytes += align256(sizeof(float) * (size_t)c * cpc * P2 * 16);
+  }
+  *ws_bytes = bytes;
+  return FCFS_OK;
+}
+
 }  // namespace fcfs
 
 using namespace fcfs;
@@ -329,25 +399,75 @@ fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   return FCFS_OK;
 }
 
+static fcfs_status backward_checks(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
+                                   int64_t h, int64_t w, int64_t c_out, bool need_dw, int64_t* ho,
+                                   int64_t* wo) {
+  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, ho, wo);
+  if (st != FCFS_OK) return st;
+  if (plan->method == FCFS_LEARNED_MIX4) return FCFS_E_UNSUPPORTED;
+  if (plan->method == FCFS_LEARNED_DW4 && plan->ah.p * plan->aw.p > 64) return FCFS_E_UNSUPPORTED;
+  if (need_dw && plan->method != FCFS_LEARNED_DW4) return FCFS_E_INVAL;
+  return FCFS_OK;
+}
+
 fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
                                     int64_t h, int64_t w, int64_t c_out, size_t* bytes) {
   int64_t ho = 0, wo = 0;
   if (!bytes) return FCFS_E_INVAL;
-  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
-  if (st != FCFS_OK) return st;
   *bytes = 0;
-  return FCFS_E_UNSUPPORTED;
+  const bool learned = plan && plan->method == FCFS_LEARNED_DW4;
+  fcfs_status st = backward_checks(plan, dtype, n, c_in, h, w, c_out, false, &ho, &wo);
+  if (st != FCFS_OK) return st;
+  if (n == 0 || c_in == 0 || h == 0 || w == 0) return FCFS_OK;
+  BwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  size_t off_w, off_p;
+  // sized for the weight gradient too when the method has weights
+  return plan_backward(plan, n, c_in, (int)h, (int)w, (int)ho, (int)wo, learned, &a, bytes, &off_w, &off_p);
 }
 
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
                           int64_t w, const void* x, const float* weight, int64_t c_out,
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
                           hipStream_t stream) {
-  (void)x; (void)weight; (void)dy; (void)dx; (void)dw; (void)workspace; (void)ws_bytes; (void)stream;
   int64_t ho = 0, wo = 0;
-  fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
+  fcfs_status st = backward_checks(plan, dtype, n, c_in, h, w, c_out, dw != nullptr, &ho, &wo);
   if (st != FCFS_OK) return st;
-  return FCFS_E_UNSUPPORTED;
+  const bool learned = plan->method == FCFS_LEARNED_DW4;
+  if (n == 0 || c_in == 0 || h == 0 || w == 0) {
+    // no samples: the weight gradient is an empty sum
+    if (dw) {
+      if (hipMemsetAsync(dw, 0, sizeof(float) * (size_t)c_in * plan->ah.p * plan->aw.p * 16, stream) !=
+          hipSuccess)
+        return FCFS_E_DEVICE;
+    }
+    return FCFS_OK;
+  }
+  if (!dx && !dw) return FCFS_OK;
+  if (!dy) return FCFS_E_INVAL;
+  if (dx && learned && !weight) return FCFS_E_INVAL;
+  if (dw && !x) return FCFS_E_INVAL;
+  if (!learned && weight) return FCFS_E_INVAL;
+  BwdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  size_t need = 0, off_w = 0, off_p = 0;
+  st = plan_backward(plan, n, c_in, (int)h, (int)w, (int)ho, (int)wo, dw != nullptr, &a, &need, &off_w, &off_p);
+  if (st != FCFS_OK) return st;
+  if (!workspace || ws_bytes < need) return FCFS_E_INVAL;
+  char* ws = static_cast<char*>(workspace);
+  a.x = x;
+  a.weight = weight;
+  a.dy = dy;
+  a.dx = dx;
+  a.dw = dw;
+  a.tab_h = reinterpret_cast<int*>(ws);
+  a.tab_w = reinterpret_cast<int*>(ws + off_w);
+  a.partial = dw ? reinterpret_cast<float*>(ws + off_p) : nullptr;
+  switch (dtype) {
+    case FCFS_F32: return launch_backward_f32(a, learned, stream);
+    case FCFS_BF16: return launch_backward_bf16(a, learned, stream);
+    default: return launch_backward_f16(a, learned, stream);
+  }
 }
 
 const char* fcfs_status_string(fcfs_status s) {

@@ -1,0 +1,232 @@
+// FCFS backward for gfx950: the adjoint of the forward (input gradient) and
+// the gradient of the learned depthwise taps.
+//
+// Adjoint tables. For each input index i of an axis the setup kernel lists the
+// (output index k, tap t) pairs whose tap reads i once the padding is applied:
+// the extended positions e that the padding maps to i (e = i itself, and for
+// replicate / reflect the positions beyond the edges that copy or mirror i),
+// and for each e every phase j and tap t with q*m + off[j] + t = e. Entries
+// are kept in ascending e, j, t order, so every sum below runs in a fixed
+// order. Table row i: [count, first k, last k, entry 0, entry 1, ...], an
+// entry packing (k << 2) | t.
+//
+// Input gradient. One thread per input sample: dx[i][c] = sum over the row
+// entries (kh, th) and column entries (kw, tw) of w * dy[kh][kw], where w is
+// the product of the two tap weights (fixed methods) or the learned weight
+// W[channel][kh mod p][kw mod p][th][tw]. No atomics: each input sample
+// gathers its own terms, so the pad adjoint (folding the gradient of padded
+// positions back onto the samples they copy) costs nothing extra.
+//
+// Weight gradient (learned depthwise). dw[c][jh][jw][a][b] = sum over batch
+// and cells of dy * ext(x). The partial kernel gives each workgroup a chunk of
+// cells of one (n, c) plane, stages the chunk's dy and padded x in LDS, and
+// has each thread accumulate the 16 taps of one phase over a fixed subset of
+// cells; subsets are then added in a fixed order. The reduce kernel adds the
+// chunks of each channel in a fixed order. Results do not depend on timing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fcfs_internal.h"
+#include "fwd_kernel.h"
+
+namespace fcfs {
+namespace bwd {
+
+using fwd::pad_source;
+using fwd::Store;
+
+constexpr int kThreads = 256;
+
+// Setup: the adjoint tables of both axes (rows 0..H-1 of the height axis,
+// then 0..W-1 of the width axis).
+template <int DT>
+__global__ __launch_bounds__(kThreads) void adjoint_tables_kernel(const BwdArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (g >= (int64_t)a.H + a.W) return;
+  const bool height = g < a.H;
+  const int i = height ? (int)g : (int)(g - a.H);
+  const AxisTable& t = height ? a.th : a.tw_tab;
+  const int n = height ? a.H : a.W;
+  const int cells = height ? a.Mh : a.Mw;
+  const int cmax = height ? a.cmax_h : a.cmax_w;
+  int* row = (height ? a.tab_h : a.tab_w) + (int64_t)i * (3 + cmax);
+  const int emin = t.omin, emax = t.q * (cells - 1) + t.omax;
+  int cnt = 0, klo = 1 << 30, khi = -1;
+  auto add_position = [&](int e) {
+    for (int j = 0; j < t.p; ++j)
+      for (int tap = 0; tap < t.T; ++tap) {
+        const int d = e - t.off[j] - tap;
+        if (d < 0 || d % t.q != 0) continue;
+        const int m = d / t.q;
+        if (m >= cells) continue;
+        const int k = t.p * m + j;
+        if (cnt < cmax) row[3 + cnt] = (k << 2) | tap;
+        ++cnt;
+        klo = min(klo, k);
+        khi = max(khi, k);
+      }
+  };
+  for (int e = emin; e < 0; ++e)
+    if (pad_source(e, n, a.pad) == i) add_position(e);
+  add_position(i);
+  for (int e = n; e <= emax; ++e)
+    if (pad_source(e, n, a.pad) == i) add_position(e);
+  row[0] = min(cnt, cmax);
+  row[1] = klo;
+  row[2] = khi;
+}
+
+template <int DT, bool LEARNED>
+__global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
+  using S = Store<DT>;
+  using TS = typename S::T;
+  const int64_t per_plane_blocks = (int64_t)a.H * a.col_blocks;
+  const int64_t plane = blockIdx.x / per_plane_blocks;
+  const int64_t rem = blockIdx.x - plane * per_plane_blocks;
+  const int i = (int)(rem / a.col_blocks);
+  const int j = (int)(rem % a.col_blocks) * kThreads + threadIdx.x;
+  if (plane >= a.planes || j >= a.W) return;
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+  const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
+  const int* rw = a.tab_w + (int64_t)j * (3 + a.cmax_w);
+  const int nh = rh[0], nw = rw[0];
+  const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
+  const float* wc = LEARNED ? a.weight + (int64_t)(plane % a.C) * TH.p * TW.p * 16 : nullptr;
+  float acc = 0.f;
+  for (int eh = 0; eh < nh; ++eh) {
+    const int ph = rh[3 + eh];
+    const int kh = ph >> 2, th = ph & 3;
+    const int jh = kh % TH.p;
+    const TS* dyrow = dyp + (int64_t)kh * a.Wo;
+    if constexpr (LEARNED) {
+      const float* wj = wc + (jh * TW.p) * 16 + th * 4;
+      for (int ew = 0; ew < nw; ++ew) {
+        const int pw = rw[3 + ew];
+        const int kw = pw >> 2, tw = pw & 3;
+        acc = __builtin_fmaf(wj[(kw % TW.p) * 16 + tw], S::load(dyrow + kw), acc);
+      }
+    } else {
+      float inner = 0.f;
+      for (int ew = 0; ew < nw; ++ew) {
+        const int pw = rw[3 + ew];
+        const int kw = pw >> 2, tw = pw & 3;
+        inner = __builtin_fmaf(TW.w[kw % TW.p][tw], S::load(dyrow + kw), inner);
+      }
+      acc = __builtin_fmaf(TH.w[jh][th], inner, acc);
+    }
+  }
+  TS* dxp = reinterpret_cast<TS*>(a.dx) + plane * (int64_t)a.H * a.W;
+  S::store(dxp + (int64_t)i * a.W + j, acc);
+}
+
+// Weight gradient, stage 1: per-chunk partial sums. A chunk is ch x cw cells
+// of one plane; block b covers channel c = b / chunks_per_channel.
+template <int DT>
+__global__ __launch_bounds__(kThreads) void dw_partial_kernel(const BwdArgs a) {
+  using S = Store<DT>;
+  using TS = typename S::T;
+  extern __shared__ float smem[];
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+  const int c = blockIdx.x / a.chunks_per_channel;
+  const int r = blockIdx.x % a.chunks_per_channel;
+  const int n = r / (a.nch * a.ncw);
+  const int cb = r % (a.nch * a.ncw);
+  const int mh0 = (cb / a.ncw) * a.ch, mw0 = (cb % a.ncw) * a.cw;
+  const int mh1 = min(mh0 + a.ch, a.Mh), mw1 = min(mw0 + a.cw, a.Mw);
+  const int64_t plane = (int64_t)n * a.C + c;
+  // staged patches: dy rows p*mh0 .. p*mh1-1, cols p*mw0 .. ; x rows from
+  // q*mh0 + omin, cols from q*mw0 + omin (padded)
+  const int dyr = TH.p * (mh1 - mh0), dyc = TW.p * (mw1 - mw0);
+  const int xr = TH.q * (mh1 - mh0 - 1) + TH.omax - TH.omin + 1;
+  const int xc = TW.q * (mw1 - mw0 - 1) + TW.omax - TW.omin + 1;
+  float* dys = smem;
+  float* xs = smem + dyr * dyc;
+  float* red = xs + xr * xc;   // [subsets][phases][16]
+  const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
+  const TS* xp = reinterpret_cast<const TS*>(a.x) + plane * (int64_t)a.H * a.W;
+  for (int idx = threadIdx.x; idx < dyr * dyc; idx += kThreads) {
+    const int rr = idx / dyc, cc = idx % dyc;
+    dys[idx] = S::load(dyp + (int64_t)(TH.p * mh0 + rr) * a.Wo + TW.p * mw0 + cc);
+  }
+  const int xr0 = TH.q * mh0 + TH.omin, xc0 = TW.q * mw0 + TW.omin;
+  for (int idx = threadIdx.x; idx < xr * xc; idx += kThreads) {
+    const int rr = idx / xc, cc = idx % xc;
+    const int sr = pad_source(xr0 + rr, a.H, a.pad), sc = pad_source(xc0 + cc, a.W, a.pad);
+    xs[idx] = (sr < 0 || sc < 0) ? 0.f : S::load(xp + (int64_t)sr * a.W + sc);
+  }
+  __syncthreads();
+  const int P2 = TH.p * TW.p;
+  const int subsets = kThreads / P2;
+  const int phase = threadIdx.x % P2, sub = threadIdx.x / P2;
+  float acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+  if (sub < subsets) {
+    const int jh = phase / TW.p, jw = phase % TW.p;
+    const int oh = TH.off[jh] - TH.omin, ow = TW.off[jw] - TW.omin;
+    const int ncell = (mh1 - mh0) * (mw1 - mw0);
+    for (int cell = sub; cell < ncell; cell += subsets) {
+      const int lh = cell / (mw1 - mw0), lw = cell % (mw1 - mw0);
+      const float g = dys[(TH.p * lh + jh) * dyc + TW.p * lw + jw];
+      const float* xb = xs + (TH.q * lh + oh) * xc + TW.q * lw + ow;
+#pragma unroll
+      for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) acc[ta * 4 + tb] = __builtin_fmaf(g, xb[ta * xc + tb], acc[ta * 4 + tb]);
+    }
+    float* rp = red + (sub * P2 + phase) * 16;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rp[k] = acc[k];
+  }
+  __syncthreads();
+  // add the subsets in a fixed order: thread t handles (phase, tap) pairs
+  float* out = a.partial + ((int64_t)c * a.chunks_per_channel + r) * P2 * 16;
+  for (int pt = threadIdx.x; pt < P2 * 16; pt += kThreads) {
+    float s = 0.f;
+    for (int sb = 0; sb < subsets; ++sb) s += red[sb * P2 * 16 + pt];
+    out[pt] = s;
+  }
+}
+
+// Weight gradient, stage 2: add the chunks of each channel in order.
+template <int DT>
+__global__ __launch_bounds__(kThreads) void dw_reduce_kernel(const BwdArgs a) {
+  const int P2 = a.th.p * a.tw_tab.p;
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (g >= (int64_t)a.C * P2 * 16) return;
+  const int c = (int)(g / (P2 * 16));
+  const int pt = (int)(g % (P2 * 16));
+  const float* src = a.partial + (int64_t)c * a.chunks_per_channel * P2 * 16 + pt;
+  float s = 0.f;
+  for (int r = 0; r < a.chunks_per_channel; ++r) s += src[(int64_t)r * P2 * 16];
+  a.dw[g] = s;   // layout [C][p_h][p_w][4][4] = [C][phase][16]
+}
+
+template <int DT>
+fcfs_status launch_backward_dt(const BwdArgs& a, bool learned, hipStream_t stream) {
+  const dim3 block(kThreads);
+  hipLaunchKernelGGL((adjoint_tables_kernel<DT>), dim3((unsigned)(((int64_t)a.H + a.W + kThreads - 1) / kThreads)),
+                     block, 0, stream, a);
+  if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  if (a.dx) {
+    const int64_t blocks = a.planes * (int64_t)a.H * a.col_blocks;
+    if (learned) hipLaunchKernelGGL((dx_kernel<DT, true>), dim3((unsigned)blocks), block, 0, stream, a);
+    else hipLaunchKernelGGL((dx_kernel<DT, false>), dim3((unsigned)blocks), block, 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  }
+  if (a.dw) {
+    hipLaunchKernelGGL((dw_partial_kernel<DT>), dim3((unsigned)(a.C * (int64_t)a.chunks_per_channel)), block,
+                       a.dw_lds_bytes, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+    const int64_t n = (int64_t)a.C * a.th.p * a.tw_tab.p * 16;
+    hipLaunchKernelGGL((dw_reduce_kernel<DT>), dim3((unsigned)((n + kThreads - 1) / kThreads)), block, 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  }
+  return FCFS_OK;
+}
+
+}  // namespace bwd
+}  // namespace fcfs

@@ -64,6 +64,32 @@ struct FwdArgs {
   AxisTable th, tw_tab;
 };
 
+struct BwdArgs {
+  const void* x;         // input (needed for the weight gradient)
+  const float* weight;   // learned depthwise taps [C][p_h][p_w][4][4] or null
+  const void* dy;        // output gradient
+  void* dx;              // input gradient or null
+  float* dw;             // weight gradient or null
+  int64_t planes;        // n * c
+  int C;
+  int H, W, Ho, Wo, Mh, Mw;
+  int pad;
+  int col_blocks;        // input-gradient blocks per input row
+  int cmax_h, cmax_w;    // adjoint table entries per index
+  int* tab_h;            // adjoint tables (workspace), see bwd_kernel.h
+  int* tab_w;
+  float* partial;        // weight-gradient partial sums (workspace)
+  int ch, cw, nch, ncw;  // weight-gradient chunk: ch x cw cells, nch x ncw chunks per plane
+  int chunks_per_channel;
+  int dw_lds_bytes;
+  AxisTable th, tw_tab;
+};
+
+// Backward kernel launchers, one per storage type (bwd_<dtype>.hip).
+fcfs_status launch_backward_f32(const BwdArgs& a, bool learned, hipStream_t stream);
+fcfs_status launch_backward_bf16(const BwdArgs& a, bool learned, hipStream_t stream);
+fcfs_status launch_backward_f16(const BwdArgs& a, bool learned, hipStream_t stream);
+
 // Forward kernel launchers, one per storage type (fwd_<dtype>.hip).
 fcfs_status launch_forward_f32(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);
 fcfs_status launch_forward_bf16(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);

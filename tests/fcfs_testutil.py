@@ -5,8 +5,11 @@ import numpy as np
 import oracle
 import synth
 
-# unit roundoff of each storage type (RNE store of an FP32 result)
+# unit roundoff of each storage type (RNE store of an FP32 result), and the
+# absolute rounding error bound in its subnormal range (half the smallest
+# subnormal spacing)
 UNIT = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+UNIT_ABS = {"f32": 2.0 ** -150, "bf16": 2.0 ** -134, "f16": 2.0 ** -25}
 # accumulation tolerance of the FP32 arithmetic, relative to S = sum |w||x|
 # (at most 16 products and one rounded weight per tap: well below 1e-5)
 ACC = 1e-5
@@ -55,7 +58,7 @@ def assert_parity(y, x, p, q, method, pad, dtype="f32", grid="half", weight=None
         return
     S = oracle.condition(x64, p, q, method, pad, grid, weight=weight, pw=pw, qw=qw)
     err = np.abs(y.astype(np.float64) - r)
-    bound = UNIT[dtype] * np.abs(r) + ACC * S + 1e-30
+    bound = UNIT[dtype] * np.abs(r) + UNIT_ABS[dtype] + ACC * S + 1e-30
     bad = err > bound
     if bad.any():
         i = np.argwhere(bad)[0]

@@ -6,9 +6,12 @@ namespace fcfs {
 namespace fwd {
 alignas(16) float smem[hostemu::kLdsFloats];
 }  // namespace fwd
+namespace bwd {
+alignas(16) float smem[hostemu::kLdsFloats];
+}  // namespace bwd
 }  // namespace fcfs
 
 namespace hostemu {
-float* const lds_arrays[] = {fcfs::fwd::smem};
+float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem};
 const int n_lds_arrays = sizeof(lds_arrays) / sizeof(lds_arrays[0]);
 }  // namespace hostemu

@@ -30,6 +30,7 @@ struct dim3 {
 namespace hostemu {
 inline thread_local dim3 tid_, bid_, grid_;
 inline thread_local std::barrier<>* wave_bar_ = nullptr;
+inline thread_local std::barrier<>* block_bar_ = nullptr;
 constexpr size_t kLdsFloats = 160 * 1024 / 4;
 }  // namespace hostemu
 
@@ -52,6 +53,7 @@ inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); r
 #define __builtin_amdgcn_readfirstlane(x) (x)
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() (hostemu::wave_bar_->arrive_and_wait())
+#define __syncthreads() (hostemu::block_bar_->arrive_and_wait())
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 #define __builtin_nontemporal_load(p) (*(p))
 
@@ -89,23 +91,42 @@ template <class K, class... A>
 inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... args) {
   if (lds > hostemu::kLdsFloats * 4) std::abort();
   const unsigned nthreads = block.x, nwaves = (nthreads + 63) / 64;
-  for (unsigned b = 0; b < grid.x; ++b) {
-    std::vector<std::unique_ptr<std::barrier<>>> bars;
-    for (unsigned w = 0; w < nwaves; ++w) bars.emplace_back(new std::barrier<>(64));
+  // One worker thread per lane, reused for every workgroup; fresh barriers per
+  // workgroup (lanes that return early drop out of them).
+  std::vector<std::unique_ptr<std::barrier<>>> bars;
+  std::unique_ptr<std::barrier<>> block_bar;
+  std::barrier<> start((std::ptrdiff_t)nthreads + 1), done((std::ptrdiff_t)nthreads + 1);
+  unsigned cur = 0;
+  auto prepare = [&](unsigned b) {
+    bars.clear();
+    for (unsigned w = 0; w < nwaves; ++w)
+      bars.emplace_back(new std::barrier<>((std::ptrdiff_t)std::min(64u, nthreads - 64 * w)));
+    block_bar.reset(new std::barrier<>((std::ptrdiff_t)nthreads));
     for (int i = 0; i < hostemu::n_lds_arrays; ++i)   // stale LDS reads as NaN
       std::memset(hostemu::lds_arrays[i], 0xff, lds);
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nthreads; ++t)
-      th.emplace_back([=, &bars] {
+    cur = b;
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nthreads; ++t)
+    th.emplace_back([&, t] {
+      for (unsigned b = 0; b < grid.x; ++b) {
+        start.arrive_and_wait();
         hostemu::tid_ = dim3(t);
-        hostemu::bid_ = dim3(b);
+        hostemu::bid_ = dim3(cur);
         hostemu::grid_ = grid;
         hostemu::wave_bar_ = bars[t / 64].get();
+        hostemu::block_bar_ = block_bar.get();
         kernel(args...);
-        // lanes of a wave that returned early no longer take part in barriers
         hostemu::wave_bar_->arrive_and_drop();
-      });
-    for (auto& x : th) x.join();
+        hostemu::block_bar_->arrive_and_drop();
+        done.arrive_and_wait();
+      }
+    });
+  for (unsigned b = 0; b < grid.x; ++b) {
+    prepare(b);
+    start.arrive_and_wait();
+    done.arrive_and_wait();
   }
+  for (auto& x : th) x.join();
 }
 #define hipLaunchKernelGGL(k, grid, block, lds, stream, ...) hostemu_launch(k, grid, block, lds, __VA_ARGS__)

@@ -22,6 +22,7 @@ PADS = {"zero": 0, "replicate": 1, "reflect": 2}
 GRIDS = {"half": 0, "paper": 1, "asym": 2}
 DT = {"f32": 0, "bf16": 1, "f16": 2}
 UNIT = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+UNIT_ABS = {"f32": 2.0 ** -150, "bf16": 2.0 ** -134, "f16": 2.0 ** -25}
 
 
 def to_storage(x, dt):
@@ -41,6 +42,37 @@ def from_storage(y, dt):
     return y.astype(np.float32)
 
 
+def run_backward(lib, plan, c, i, xs, xv, w, N, C, H, W, Ho, Wo, p, q, pw, qw, m, pad, grid, dt):
+    dyv = synth.normal(3000 + i, (N, C, Ho, Wo))
+    dys, dyv = to_storage(dyv, dt)
+    need_dw = m == "dw4"
+    ws = ctypes.c_size_t()
+    assert lib.fcfs_backward_workspace(plan, DT[dt], N, C, H, W, C, ctypes.byref(ws)) == 0
+    wsb = np.zeros(max(1, ws.value) // 4 + 64, dtype=np.int32)
+    dx = np.zeros((N, C, H, W), dtype=xs.dtype)
+    dw = np.zeros_like(w) if need_dw else None
+    st = lib.fcfs_backward(plan, DT[dt], N, C, H, W, xs.ctypes.data, None if w is None else w.ctypes.data, C,
+                           dys.ctypes.data, dx.ctypes.data, None if dw is None else dw.ctypes.data,
+                           wsb.ctypes.data, ws.value, None)
+    assert st == 0, st
+    rdx, rdw = oracle.backward(dyv.astype(np.float64), (N, C, H, W), p, q, m, pad, grid, x=xv, weight=w,
+                               need_dw=need_dw, pw=pw, qw=qw)
+    sdx, sdw = oracle.condition_backward(dyv, (N, C, H, W), p, q, m, pad, grid, x=xv, weight=w,
+                                         need_dw=need_dw, pw=pw, qw=qw)
+    gdx = from_storage(dx, dt).astype(np.float64)
+    ok = bool((np.abs(gdx - rdx) <= UNIT[dt] * np.abs(rdx) + UNIT_ABS[dt] + 1e-5 * sdx + 1e-30).all())
+    if not ok:
+        bad = np.argwhere(np.abs(gdx - rdx) > UNIT[dt] * np.abs(rdx) + UNIT_ABS[dt] + 1e-5 * sdx + 1e-30)
+        print("dx first bad", bad[:5].tolist(), gdx[tuple(bad[0])], rdx[tuple(bad[0])], flush=True)
+    if need_dw:
+        okw = bool((np.abs(dw - rdw) <= 1e-5 * sdw + 1e-30).all())
+        if not okw:
+            bad = np.argwhere(np.abs(dw - rdw) > 1e-5 * sdw + 1e-30)
+            print("dw first bad", bad[:5].tolist(), dw[tuple(bad[0])], rdw[tuple(bad[0])], flush=True)
+        ok = ok and okw
+    return ok
+
+
 def main():
     lib = ctypes.CDLL(sys.argv[1])
     cases = json.loads(sys.argv[2])
@@ -49,6 +81,9 @@ def main():
     lib.fcfs_forward.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 4 + [P, P, ctypes.c_int64, P, P]
     lib.fcfs_output_size.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.fcfs_backward_workspace.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 5 + [ctypes.POINTER(ctypes.c_size_t)]
+    lib.fcfs_backward.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 4 + [P, P, ctypes.c_int64, P, P, P, P,
+                                                                             ctypes.c_size_t, P]
     for i, c in enumerate(cases):
         p, q, pw, qw = c["p"], c["q"], c.get("pw", c["p"]), c.get("qw", c["q"])
         N, C, H, W = c["shape"]
@@ -63,6 +98,13 @@ def main():
         if m == "dw4":
             from math import gcd
             w = synth.normal(2000 + i, (C, p // gcd(p, q), pw // gcd(pw, qw), 4, 4)).astype(np.float32)
+        if c.get("mode") == "bwd":
+            ok = run_backward(lib, plan, c, i, xs, xv, w, N, C, H, W, ho.value, wo.value, p, q, pw, qw, m, pad,
+                              grid, dt)
+            print("case", i, json.dumps(c), "ok" if ok else "MISMATCH", flush=True)
+            if not ok:
+                sys.exit(1)
+            continue
         y = np.zeros((N, C, ho.value, wo.value), dtype=xs.dtype)
         st = lib.fcfs_forward(plan, DT[dt], N, C, H, W, xs.ctypes.data, None if w is None else w.ctypes.data,
                               C, y.ctypes.data, None)
@@ -73,7 +115,7 @@ def main():
             ok = np.array_equal(yv, r)
         else:
             S = oracle.condition(xv, p, q, m, pad, grid, weight=w, pw=pw, qw=qw)
-            ok = bool((np.abs(yv - r) <= UNIT[dt] * np.abs(r) + 1e-5 * S + 1e-30).all())
+            ok = bool((np.abs(yv - r) <= UNIT[dt] * np.abs(r) + UNIT_ABS[dt] + 1e-5 * S + 1e-30).all())
         print("case", i, json.dumps(c), "ok" if ok else "MISMATCH", flush=True)
         if not ok:
             bad = np.argwhere(np.abs(yv - r) > 1e-5 * np.abs(r) + 1e-6)

@@ -70,3 +70,27 @@ def test_learned_depthwise(pq):
     p, q = pq
     _run([{"p": p, "q": q, "method": "dw4", "pad": pad, "shape": [2, 3, 21, 75]}
           for pad in ["zero", "replicate", "reflect"]])
+
+
+def test_backward_fixed_methods():
+    cases = []
+    for (p, q) in [(3, 2), (2, 3), (3, 4), (27, 11), (2, 11), (1, 1), (4, 1)]:
+        for m in ["nearest", "bilinear", "bicubic"]:
+            for pad in ["zero", "replicate", "reflect"]:
+                cases.append({"mode": "bwd", "p": p, "q": q, "method": m, "pad": pad, "shape": [1, 2, 13, 70]})
+    _run(cases)
+
+
+def test_backward_learned_and_edges():
+    cases = []
+    for (p, q) in [(3, 4), (3, 2), (5, 4), (2, 11)]:
+        for pad in ["zero", "replicate", "reflect"]:
+            cases.append({"mode": "bwd", "p": p, "q": q, "method": "dw4", "pad": pad, "shape": [2, 3, 21, 75]})
+    cases += [{"mode": "bwd", "p": 3, "q": 2, "method": "bicubic", "pad": "reflect", "shape": [1, 1, 1, 1]},
+              {"mode": "bwd", "p": 3, "q": 2, "method": "dw4", "pad": "reflect", "shape": [1, 1, 2, 3]},
+              {"mode": "bwd", "p": 3, "q": 2, "method": "bicubic", "pad": "replicate", "dtype": "bf16",
+               "shape": [1, 2, 9, 40]},
+              {"mode": "bwd", "p": 3, "q": 4, "method": "dw4", "pad": "zero", "dtype": "bf16", "shape": [2, 2, 16, 40]},
+              {"mode": "bwd", "p": 3, "q": 2, "pw": 4, "qw": 5, "method": "bicubic", "pad": "zero",
+               "shape": [1, 1, 11, 30]}]
+    _run(cases)
