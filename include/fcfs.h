@@ -117,21 +117,24 @@ fcfs_status fcfs_output_size(fcfs_plan_t plan, int64_t h, int64_t w, int64_t* h_
 
 /* Forward rescale: y = FCFS(x) (Sec. 3.1 / Sec. 4.2 pseudocode).
  *   x      : device, [n][c_in][h][w] of dtype.
- *   weight : device FP32. NULL for fixed methods. LEARNED_DW4: [c_in][p_h][p_w][4][4],
+ *   weight : device. NULL for fixed methods. LEARNED_DW4: FP32 [c_in][p_h][p_w][4][4],
  *            4x4 taps per channel and phase, tap (a, b) reading input row
  *            q*m_h + floor(u_h) - 1 + a and column q*m_w + floor(u_w) - 1 + b.
- *            LEARNED_MIX4: [p_h][p_w][c_out][c_in][4][4], same taps, summed over c_in.
+ *            LEARNED_MIX4: [p_h][p_w][c_out][c_in][4][4] in the storage type
+ *            (BF16 or FP16; the layer runs on 16-bit MFMA with FP32
+ *            accumulation), 16-byte aligned; same taps, summed over c_in.
  *   c_out  : output channels; must equal c_in except for LEARNED_MIX4.
  *   y      : device, [n][c_out][h_out][w_out] of dtype; must not overlap x.
  *   stream : HIP stream the kernels are enqueued on (0 = the null stream).
  * An empty problem (n, c_in, h or w equal to 0) is valid and enqueues nothing;
  * its pointers are not inspected.
  * Errors: FCFS_E_INVAL (negative sizes, null pointers, weight missing for a learned
- * method or given for a fixed one, c_out mismatch), FCFS_E_UNSUPPORTED (a
- * per-plane size at or above 2^31 samples, dtype not built for the method),
- * FCFS_E_DEVICE (launch failed). */
+ * method or given for a fixed one, c_out mismatch, a misaligned MIX4 weight),
+ * FCFS_E_UNSUPPORTED (a per-plane size at or above 2^31 samples, LEARNED_MIX4
+ * with FP32 storage, LEARNED_DW4 with more than 64 phases), FCFS_E_DEVICE
+ * (launch failed). */
 fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
-                         int64_t w, const void* x, const float* weight, int64_t c_out, void* y,
+                         int64_t w, const void* x, const void* weight, int64_t c_out, void* y,
                          hipStream_t stream);
 
 /* Launch geometry fcfs_forward would use for these sizes (introspection for
@@ -159,11 +162,12 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
  *        only. Overwritten (not accumulated). Deterministic: the summation
  *        order is fixed by the sizes alone.
  *   x  : needed iff dw != NULL. weight: needed for learned methods iff dx != NULL.
+ *   LEARNED_MIX4 has no backward in this version (FCFS_E_UNSUPPORTED).
  *   workspace / ws_bytes: device scratch of at least fcfs_backward_workspace
  *        bytes (NULL allowed when that is 0).
  * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small. */
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
-                          int64_t w, const void* x, const float* weight, int64_t c_out,
+                          int64_t w, const void* x, const void* weight, int64_t c_out,
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
                           hipStream_t stream);
 

@@ -332,8 +332,56 @@ static fcfs_status check_common(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   return FCFS_OK;
 }
 
+// Channel-mixing layer: 16-bit storage only, weights in the storage type.
+static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                                int64_t w, int64_t ho, int64_t wo, const void* x, const void* weight,
+                                int64_t c_out, void* y, hipStream_t stream) {
+  if (dtype == FCFS_F32) return FCFS_E_UNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(weight) & 15) != 0) return FCFS_E_INVAL;
+  if (n > INT32_MAX || c_in > INT32_MAX || c_out > INT32_MAX) return FCFS_E_UNSUPPORTED;
+  MixArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.w = weight;
+  a.y = y;
+  a.N = (int)n;
+  a.Cin = (int)c_in;
+  a.Cout = (int)c_out;
+  a.H = (int)h;
+  a.W = (int)w;
+  a.Ho = (int)ho;
+  a.Wo = (int)wo;
+  a.Mh = (int)(ho / plan->ah.p);
+  a.Mw = (int)(wo / plan->aw.p);
+  a.pad = plan->pad;
+  a.th = plan->ah;
+  a.tw_tab = plan->aw;
+  a.tw_cells = 32;
+  a.th_cells = 4;
+  a.tiles_h = (a.Mh + a.th_cells - 1) / a.th_cells;
+  a.tiles_w = (a.Mw + a.tw_cells - 1) / a.tw_cells;
+  a.groups = (plan->aw.p + 4) / 5;
+  a.otiles = (int)((c_out + 63) / 64);
+  const int P = std::min(5, plan->aw.p);
+  const int R = plan->ah.q * (a.th_cells - 1) + 4;
+  int spread = 0;
+  for (int g = 0; g < a.groups; ++g) {
+    const int j0 = g * 5, j1 = std::min(plan->aw.p, j0 + 5) - 1;
+    spread = std::max(spread, plan->aw.off[j1] - plan->aw.off[j0]);
+  }
+  const int Cc = (plan->aw.q * (a.tw_cells - 1) + spread + 4 + 1) & ~1;
+  const size_t stage = ((2 * sizeof(uint16_t) * (size_t)R * Cc + 15) & ~(size_t)15) + sizeof(uint16_t) * (size_t)P * 64 * 2 * 16;
+  const size_t epi = sizeof(uint16_t) * 16 * (size_t)a.th_cells * a.tw_cells * P;
+  const size_t lds = std::max(stage, epi) + 16;
+  if (lds > 65536) return FCFS_E_UNSUPPORTED;
+  a.lds_bytes = (int)lds;
+  const int64_t blocks = n * (int64_t)a.tiles_h * a.tiles_w * plan->ah.p * a.groups * a.otiles;
+  if (blocks >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
+  return launch_mix4(dtype, a, stream);
+}
+
 fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
-                         int64_t w, const void* x, const float* weight, int64_t c_out, void* y,
+                         int64_t w, const void* x, const void* weight, int64_t c_out, void* y,
                          hipStream_t stream) {
   int64_t ho = 0, wo = 0;
   fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, &ho, &wo);
@@ -342,14 +390,14 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
   if (n == 0 || c_in == 0 || c_out == 0 || h == 0 || w == 0) return FCFS_OK;   // nothing to do
   if (!x || !y) return FCFS_E_INVAL;
   if (learned != (weight != nullptr)) return FCFS_E_INVAL;
-  if (plan->method == FCFS_LEARNED_MIX4) return FCFS_E_UNSUPPORTED;
+  if (plan->method == FCFS_LEARNED_MIX4) return forward_mix4(plan, dtype, n, c_in, h, w, ho, wo, x, weight, c_out, y, stream);
   if (plan->method == FCFS_LEARNED_DW4 && plan->ah.p * plan->aw.p > 64) return FCFS_E_UNSUPPORTED;
 
   FwdArgs a;
   std::memset(&a, 0, sizeof(a));
   a.x = x;
   a.y = y;
-  a.weight = weight;
+  a.weight = static_cast<const float*>(weight);
   a.planes = n * c_in;
   a.C = (int)c_in;
   a.H = (int)h;
@@ -427,7 +475,7 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
 }
 
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
-                          int64_t w, const void* x, const float* weight, int64_t c_out,
+                          int64_t w, const void* x, const void* weight, int64_t c_out,
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
                           hipStream_t stream) {
   int64_t ho = 0, wo = 0;
@@ -456,7 +504,7 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
   if (!workspace || ws_bytes < need) return FCFS_E_INVAL;
   char* ws = static_cast<char*>(workspace);
   a.x = x;
-  a.weight = weight;
+  a.weight = static_cast<const float*>(weight);
   a.dy = dy;
   a.dx = dx;
   a.dw = dw;

@@ -85,6 +85,22 @@ struct BwdArgs {
   AxisTable th, tw_tab;
 };
 
+struct MixArgs {
+  const void* x;         // [N][Cin][H][W], 16-bit storage
+  const void* w;         // [p_h][p_w][Cout][Cin][4][4], same storage type, 16-byte aligned
+  void* y;               // [N][Cout][Ho][Wo]
+  int N, Cin, Cout;
+  int H, W, Ho, Wo, Mh, Mw;
+  int pad;
+  int th_cells, tw_cells;    // cell tile of a workgroup
+  int tiles_h, tiles_w, groups, otiles;
+  int lds_bytes;
+  AxisTable th, tw_tab;
+};
+
+// Channel-mixing launchers (mix4.hip); dtype FCFS_BF16 or FCFS_F16.
+fcfs_status launch_mix4(int dtype, const MixArgs& a, hipStream_t stream);
+
 // Backward kernel launchers, one per storage type (bwd_<dtype>.hip).
 fcfs_status launch_backward_f32(const BwdArgs& a, bool learned, hipStream_t stream);
 fcfs_status launch_backward_bf16(const BwdArgs& a, bool learned, hipStream_t stream);

@@ -84,3 +84,21 @@ def oracle_band(xplane, p, q, method, pad, m_lo, m_hi, grid="half", weight=None,
     full = oracle.forward(crop, p, q, method, pad, grid, weight=weight, pw=pw, qw=qw)[0, 0]
     c0 = start // qr
     return full[pr * (m_lo - c0): pr * (m_hi - c0)]
+
+
+def oracle_crop(x, p, q, method, pad, mh, mw, weight=None, cout=None):
+    """Oracle outputs of cells mh = (lo, hi) x mw = (lo, hi) of every plane,
+    computed from a crop of the input that holds every sample those cells
+    read (crop starts on multiples of q, with q+2 samples of margin)."""
+    from math import gcd
+    g = gcd(p, q)
+    pr, qr = p // g, q // g
+    N, C, H, W = x.shape
+    r0, r1 = max(0, qr * (mh[0] - 2)), min(H, qr * (mh[1] + 2))
+    c0, c1 = max(0, qr * (mw[0] - 2)), min(W, qr * (mw[1] + 2))
+    crop = np.asarray(x[:, :, r0:r1, c0:c1], dtype=np.float64)
+    full = oracle.forward(crop, p, q, method, pad, weight=weight, cout=cout)
+    # a crop that stops inside the image has a different edge; only cells whose
+    # taps stay inside the crop are returned, and those do not see that edge
+    a, b = r0 // qr, c0 // qr
+    return full[:, :, pr * (mh[0] - a): pr * (mh[1] - a), pr * (mw[0] - b): pr * (mw[1] - b)]

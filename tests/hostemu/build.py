@@ -7,13 +7,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2203_10670_amd", "csrc")
 OUT = os.path.join(HERE, "_build", "libfcfs_hostemu.so")
-SOURCES = ["api.cpp", "fwd_f32.hip", "fwd_bf16.hip", "fwd_f16.hip", "bwd_f32.hip", "bwd_bf16.hip", "bwd_f16.hip"]
+SOURCES = ["api.cpp", "fwd_f32.hip", "fwd_bf16.hip", "fwd_f16.hip", "bwd_f32.hip", "bwd_bf16.hip", "bwd_f16.hip",
+           "mix4.hip"]
+CXX = "/opt/rocm/llvm/bin/clang++"   # host compile; knows __bf16, _Float16 and vector extensions
 
 
 def build(sanitize: bool = True) -> str:
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES] + [os.path.join(HERE, "emu_main.cpp")]
-    newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(HERE, "hip", "hip_runtime.h")])
+    newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(HERE, "hip", "hip_runtime.h"), __file__,
+                                                       os.path.join(CSRC, "fcfs_internal.h")] +
+                 [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")])
     if os.path.exists(OUT) and os.path.getmtime(OUT) >= newest:
         return OUT
     flags = ["-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-w",
@@ -26,19 +30,19 @@ def build(sanitize: bool = True) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        subprocess.check_call(["g++"] + [f for f in flags if f != "-shared"] + ["-c", "-x", "c++", src, "-o", obj])
+        subprocess.check_call([CXX] + [f for f in flags if f != "-shared"] + ["-c", "-x", "c++", src, "-o", obj])
         return obj
 
     with ThreadPoolExecutor(max(1, min(len(srcs), os.cpu_count() or 2))) as ex:
         objs = list(ex.map(compile_one, srcs))
     tmp = OUT + ".tmp%d" % os.getpid()
-    subprocess.check_call(["g++"] + flags + objs + ["-o", tmp])
+    subprocess.check_call([CXX] + flags + ["-shared-libsan"] + objs + ["-o", tmp])
     os.replace(tmp, OUT)
     return OUT
 
 
 def asan_runtime() -> str:
-    return subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+    return subprocess.check_output([CXX, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
 
 
 if __name__ == "__main__":

@@ -9,9 +9,12 @@ alignas(16) float smem[hostemu::kLdsFloats];
 namespace bwd {
 alignas(16) float smem[hostemu::kLdsFloats];
 }  // namespace bwd
+namespace mix {
+alignas(16) float smem[hostemu::kLdsFloats];
+}  // namespace mix
 }  // namespace fcfs
 
 namespace hostemu {
-float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem};
+float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem, fcfs::mix::smem};
 const int n_lds_arrays = sizeof(lds_arrays) / sizeof(lds_arrays[0]);
 }  // namespace hostemu

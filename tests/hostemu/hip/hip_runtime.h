@@ -57,7 +57,13 @@ inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); r
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 #define __builtin_nontemporal_load(p) (*(p))
 
-// IEEE binary16 storage with round-to-nearest-even conversion from float.
+struct uint4 {
+  unsigned x, y, z, w;
+};
+
+#ifndef __clang__
+// IEEE binary16 storage with round-to-nearest-even conversion from float
+// (clang has the type natively).
 struct _Float16 {
   uint16_t bits;
   _Float16() = default;
@@ -86,6 +92,39 @@ struct _Float16 {
     return __uint_as_float(sign | ((e + 112) << 23) | (m << 13));
   }
 };
+#endif
+
+// Matrix-core instructions, emulated for one wave: every lane publishes its
+// A and B fragments, then computes its own D entries. Operand layout of the
+// 16x16x32 forms: A lane l = row l%16, k = 8*(l/16)+i; B lane l = column l%16,
+// same k; D lane l = column l%16, rows 4*(l/16)+i.
+namespace hostemu {
+struct WaveScratch {
+  float a[64][8], b[64][8];
+};
+inline thread_local WaveScratch* wave_scratch_ = nullptr;
+template <class V8, class F4>
+inline F4 mfma_16x16x32(V8 a, V8 b, F4 c) {
+  const int l = (int)(tid_.x & 63);
+  WaveScratch* s = wave_scratch_;
+  for (int i = 0; i < 8; ++i) {
+    s->a[l][i] = (float)a[i];
+    s->b[l][i] = (float)b[i];
+  }
+  wave_bar_->arrive_and_wait();
+  F4 out = c;
+  for (int i = 0; i < 4; ++i) {
+    const int m = 4 * (l / 16) + i, n = l % 16;
+    float acc = 0.f;
+    for (int k = 0; k < 32; ++k) acc += s->a[m + 16 * (k / 8)][k % 8] * s->b[n + 16 * (k / 8)][k % 8];
+    out[i] += acc;
+  }
+  wave_bar_->arrive_and_wait();
+  return out;
+}
+}  // namespace hostemu
+#define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) hostemu::mfma_16x16x32(a, b, c)
+#define __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, x, y, z) hostemu::mfma_16x16x32(a, b, c)
 
 template <class K, class... A>
 inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... args) {
@@ -96,6 +135,7 @@ inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... arg
   std::vector<std::unique_ptr<std::barrier<>>> bars;
   std::unique_ptr<std::barrier<>> block_bar;
   std::barrier<> start((std::ptrdiff_t)nthreads + 1), done((std::ptrdiff_t)nthreads + 1);
+  std::vector<hostemu::WaveScratch> scratch(nwaves);
   unsigned cur = 0;
   auto prepare = [&](unsigned b) {
     bars.clear();
@@ -116,6 +156,7 @@ inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... arg
         hostemu::grid_ = grid;
         hostemu::wave_bar_ = bars[t / 64].get();
         hostemu::block_bar_ = block_bar.get();
+        hostemu::wave_scratch_ = &scratch[t / 64];
         kernel(args...);
         hostemu::wave_bar_->arrive_and_drop();
         hostemu::block_bar_->arrive_and_drop();

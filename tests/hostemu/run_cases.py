@@ -17,7 +17,7 @@ sys.path.insert(0, os.path.dirname(HERE))
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-METHODS = {"nearest": 0, "bilinear": 1, "bicubic": 2, "dw4": 3}
+METHODS = {"nearest": 0, "bilinear": 1, "bicubic": 2, "dw4": 3, "mix4": 4}
 PADS = {"zero": 0, "replicate": 1, "reflect": 2}
 GRIDS = {"half": 0, "paper": 1, "asym": 2}
 DT = {"f32": 0, "bf16": 1, "f16": 2}
@@ -95,9 +95,18 @@ def main():
         x = synth.normal(1000 + i, (N, C, H, W))
         xs, xv = to_storage(x, dt)
         w = None
+        wptr = None
+        Co = C
+        from math import gcd
         if m == "dw4":
-            from math import gcd
             w = synth.normal(2000 + i, (C, p // gcd(p, q), pw // gcd(pw, qw), 4, 4)).astype(np.float32)
+            wptr = w.ctypes.data
+        if m == "mix4":
+            Co = c.get("cout", C)
+            wraw = synth.normal(2000 + i, (p // gcd(p, q), pw // gcd(pw, qw), Co, C, 4, 4), std=1 / 32)
+            wbits, w = to_storage(wraw, dt)
+            wbits = np.ascontiguousarray(wbits)
+            wptr = wbits.ctypes.data
         if c.get("mode") == "bwd":
             ok = run_backward(lib, plan, c, i, xs, xv, w, N, C, H, W, ho.value, wo.value, p, q, pw, qw, m, pad,
                               grid, dt)
@@ -105,16 +114,21 @@ def main():
             if not ok:
                 sys.exit(1)
             continue
-        y = np.zeros((N, C, ho.value, wo.value), dtype=xs.dtype)
-        st = lib.fcfs_forward(plan, DT[dt], N, C, H, W, xs.ctypes.data, None if w is None else w.ctypes.data,
-                              C, y.ctypes.data, None)
+        y = np.zeros((N, Co, ho.value, wo.value), dtype=xs.dtype)
+        st = lib.fcfs_forward(plan, DT[dt], N, C, H, W, xs.ctypes.data, wptr, Co, y.ctypes.data, None)
+        if c.get("expect_status") is not None:
+            ok = st == c["expect_status"]
+            print("case", i, json.dumps(c), "ok" if ok else "MISMATCH status %d" % st, flush=True)
+            if not ok:
+                sys.exit(1)
+            continue
         assert st == 0, st
         yv = from_storage(y, dt).astype(np.float64)
-        r = oracle.forward(xv.astype(np.float64), p, q, m, pad, grid, weight=w, pw=pw, qw=qw)
+        r = oracle.forward(xv.astype(np.float64), p, q, m, pad, grid, weight=w, pw=pw, qw=qw, cout=Co)
         if m == "nearest":
             ok = np.array_equal(yv, r)
         else:
-            S = oracle.condition(xv, p, q, m, pad, grid, weight=w, pw=pw, qw=qw)
+            S = oracle.condition(xv, p, q, m, pad, grid, weight=w, pw=pw, qw=qw, cout=Co)
             ok = bool((np.abs(yv - r) <= UNIT[dt] * np.abs(r) + UNIT_ABS[dt] + 1e-5 * S + 1e-30).all())
         print("case", i, json.dumps(c), "ok" if ok else "MISMATCH", flush=True)
         if not ok:

@@ -94,3 +94,16 @@ def test_backward_learned_and_edges():
               {"mode": "bwd", "p": 3, "q": 2, "pw": 4, "qw": 5, "method": "bicubic", "pad": "zero",
                "shape": [1, 1, 11, 30]}]
     _run(cases)
+
+
+def test_channel_mixing_mfma():
+    cases = []
+    for dt in ["bf16", "f16"]:
+        for (p, q, pad) in [(5, 4, "reflect"), (3, 2, "zero"), (2, 3, "replicate"), (7, 5, "reflect")]:
+            cases.append({"p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": [1, 6, 13, 40],
+                          "cout": 5})
+    cases.append({"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "bf16", "shape": [2, 4, 9, 150],
+                  "cout": 70})
+    cases.append({"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 2, 8, 8],
+                  "cout": 2, "expect_status": 2})
+    _run(cases)
