@@ -34,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_BF16_TFLOPS = 2500.0
 FRACS = [(3, 2), (2, 3), (5, 4), (4, 5)]
 METHODS = ["nearest", "bilinear", "bicubic"]
 PADS = ["zero", "reflect"]
@@ -80,6 +81,113 @@ def load_traffic(kernel_id: int):
         return None
     e = d.get("kernels", {}).get(str(kernel_id))
     return None if e is None else e.get("bytes_per_launch")
+
+
+def bicubic_dw4_init(p, q, C, seed):
+    """Learned depthwise 4x4 taps initialised to the bicubic outer product
+    (the plan's own taps) plus N(0, 0.01) noise, for every channel."""
+    import paper_2203_10670_amd as fc
+    import synth
+    pl = fc.Plan(p, q, "bicubic", "zero")
+    t = np.array([fc.fcfs_plan_taps(pl.handle, 0, j)[1] for j in range(pl.p_red)], dtype=np.float64)
+    base = np.einsum("ia,jb->ijab", t, t)[None].repeat(C, axis=0)
+    return (base + synth.normal(seed, base.shape, std=0.1)).astype(np.float32)
+
+
+def measure_rows(reps: int):
+    """The other workloads of the hot path, each timed on its own:
+    - 16x64x512x512 N(0,1) bicubic 5/4 forward, FP32 and BF16 storage;
+    - the channel-mixing layer on MFMA on the same BF16 input (64 -> 64);
+    - the learned depthwise layer 8x64x256x256 at 3/4: forward and backward
+      (input and weight gradients), FP32 and BF16, over 3 rotating buffer sets
+      (one set fits in the 256 MB last-level cache)."""
+    import torch
+    import paper_2203_10670_amd as fc
+    import synth
+    dev = torch.device("cuda:0")
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    out = {}
+
+    def timeit(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(n):
+            fn(i)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1000.0 / n
+
+    # 16 x 64 x 512^2, 5/4 bicubic
+    N, C, H, W = 16, 64, 512, 512
+    x32 = torch.from_numpy(synth.normal(4, (N, C, H, W))).to(dev)
+    pl = fc.Plan(5, 4, "bicubic", "reflect")
+    ho, wo = pl.output_size(H, W)
+    for name, xt, es in (("f32", x32, 4), ("bf16", x32.to(torch.bfloat16), 2)):
+        y = torch.empty((N, C, ho, wo), dtype=xt.dtype, device=dev)
+        code = fc.DTYPES[name]
+
+        def run(i=0):
+            st = fc.fcfs_forward(pl.handle, code, N, C, H, W, xt.data_ptr(), None, C, y.data_ptr(), sp)
+            assert st == 0
+        us = timeit(run, reps)
+        b = case_bytes(fc, pl, (N, C, H, W), es)
+        out["bicubic_5_4_16x64x512_" + name] = {"us": round(us, 2), "bytes": b, "GBps": round(b / us / 1e3, 1)}
+        del y
+    # channel mixing on MFMA, BF16
+    xb = x32.to(torch.bfloat16)
+    del x32
+    wm = torch.from_numpy(synth.normal(5, (5, 5, C, C, 4, 4), std=1 / 32)).to(dev).to(torch.bfloat16)
+    plm = fc.Plan(5, 4, "mix4", "reflect")
+    ym = torch.empty((N, C, ho, wo), dtype=torch.bfloat16, device=dev)
+
+    def runm(i=0):
+        st = fc.fcfs_forward(plm.handle, 1, N, C, H, W, xb.data_ptr(), wm.data_ptr(), C, ym.data_ptr(), sp)
+        assert st == 0
+    us = timeit(runm, max(3, reps // 2))
+    flops = 2.0 * N * (ho // 5) * (wo // 5) * 25 * C * C * 16
+    out["mix4_5_4_16x64x512_bf16"] = {"us": round(us, 2), "flop": flops,
+                                      "TFLOPs": round(flops / us / 1e6, 1),
+                                      "mfma_frac": round(flops / us / 1e6 / MFMA_PEAK_BF16_TFLOPS, 4)}
+    del xb, wm, ym
+    torch.cuda.empty_cache()
+    # learned depthwise 8 x 64 x 256^2 at 3/4, forward and backward
+    N, C, H, W, p, q = 8, 64, 256, 256, 3, 4
+    pld = fc.Plan(p, q, "dw4", "reflect")
+    ho, wo = pld.output_size(H, W)
+    wd = torch.from_numpy(bicubic_dw4_init(p, q, C, 7)).to(dev)
+    for name, es in (("f32", 4), ("bf16", 2)):
+        td = torch.float32 if name == "f32" else torch.bfloat16
+        code = fc.DTYPES[name]
+        sets = []
+        for k in range(3):
+            xt = torch.from_numpy(synth.normal(6 + 10 * k, (N, C, H, W))).to(dev).to(td)
+            dyt = torch.from_numpy(synth.normal(8 + 10 * k, (N, C, ho, wo))).to(dev).to(td)
+            sets.append((xt, dyt, torch.empty((N, C, ho, wo), dtype=td, device=dev),
+                         torch.empty((N, C, H, W), dtype=td, device=dev)))
+        dw = torch.empty_like(wd)
+        wsb = fc.fcfs_backward_workspace(pld.handle, code, N, C, H, W, C)
+        ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+
+        def fwd(i=0):
+            xt, _, yt, _ = sets[i % 3]
+            assert fc.fcfs_forward(pld.handle, code, N, C, H, W, xt.data_ptr(), wd.data_ptr(), C, yt.data_ptr(), sp) == 0
+
+        def bwd(i=0):
+            xt, dyt, _, dxt = sets[i % 3]
+            assert fc.fcfs_backward(pld.handle, code, N, C, H, W, xt.data_ptr(), wd.data_ptr(), C, dyt.data_ptr(),
+                                    dxt.data_ptr(), dw.data_ptr(), ws.data_ptr(), wsb, sp) == 0
+        uf = timeit(fwd, reps)
+        ub = timeit(bwd, reps)
+        bf = (N * C * H * W + N * C * ho * wo) * es
+        bb = (N * C * ho * wo + 2 * N * C * H * W) * es
+        out["dw4_3_4_8x64x256_" + name] = {"fwd_us": round(uf, 2), "fwd_GBps": round(bf / uf / 1e3, 1),
+                                           "bwd_us": round(ub, 2), "bwd_GBps": round(bb / ub / 1e3, 1),
+                                           "fwd_bytes": bf, "bwd_bytes": bb}
+        del sets, ws
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(cases, x_np, target_planes: int):
@@ -140,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=0)
+    ap.add_argument("--no-rows", action="store_true", help="skip the other workloads (mix4, learned layer, ...)")
     ap.add_argument("--filter", default="", help="only cases whose name contains this text")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -230,8 +339,10 @@ def main():
         del a_, b_
 
     f32 = make_cases("f32", x32, 4)
+    f32_meta = [{k: c[k] for k in ("p", "q", "method", "pad", "bytes")} for c in f32]
     if args.filter:
         f32 = [c for c in f32 if args.filter in "%d/%d %s %s" % (c["p"], c["q"], c["method"], c["pad"])]
+        f32_meta = [c for c in f32_meta if args.filter in "%d/%d %s %s" % (c["p"], c["q"], c["method"], c["pad"])]
     ms_step = timed_sweep(f32, args.steps, args.warmup)
     step_bytes = sum(c["bytes"] for c in f32)
     value = step_bytes / (ms_step * 1e-3) / 1e9
@@ -260,7 +371,6 @@ def main():
                           "kernel_id": c["kernel_id"]} for c, us in pc]}
     bf16_value = None
     if not args.no_bf16 and not args.filter:
-        del pc
         bf = make_cases("bf16", xbf, 2)
         ms_bf = timed_sweep(bf, args.steps, args.warmup)
         bf16_value = sum(c["bytes"] for c in bf) / (ms_bf * 1e-3) / 1e9
@@ -273,9 +383,15 @@ def main():
         del bf, pcb
     torch.cuda.synchronize()
 
+    rows = None
+    if not args.no_rows and not args.filter:
+        del f32, pc, x32, xbf
+        torch.cuda.empty_cache()
+        rows = measure_rows(max(3, args.steps))
+
     cpu = None
     if not args.no_cpu_baseline and not args.filter:
-        cpu = cpu_baseline(f32, x_np, args.cpu_planes)
+        cpu = cpu_baseline(f32_meta, x_np, args.cpu_planes)
 
     line = {
         "metric": "resample output GB/s vs HBM peak (FP32, BF16); served p50/p99 latency",
@@ -285,11 +401,12 @@ def main():
         "config": {"workload": "FCFS forward sweep: N=32 C=3 1024x1024 FP32 U[0,1); scales 3/2 2/3 5/4 4/5; "
                                "nearest bilinear bicubic; zero and reflect padding (24 launches per step)",
                    "batch": SHAPE[0], "channels": SHAPE[1], "height": SHAPE[2], "width": SHAPE[3],
-                   "launches_per_step": len(f32), "bytes_per_step": step_bytes},
+                   "launches_per_step": len(f32_meta), "bytes_per_step": step_bytes},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bf16_value": None if bf16_value is None else round(bf16_value, 1),
         "breakdown": breakdown,
+        "rows": rows,
     }
     print(json.dumps(line), flush=True)
 
