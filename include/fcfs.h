@@ -171,6 +171,80 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
                           hipStream_t stream);
 
+/* ------------------------------------------------------------------ serving
+ * A persistent request loop on one GPU (continuous batching). Clients submit
+ * rescale requests from any thread; a scheduler thread admits pending
+ * requests while request slots and the device memory budget allow, and
+ * launches one batched forward kernel per scheduling tick covering every
+ * newly admitted request (mixed sizes, factors, methods and storage types),
+ * alternating two HIP streams so that requests arriving while a batch runs
+ * are launched next to it. Buffers stay on the device. A completion thread
+ * timestamps finished batches. Results equal fcfs_forward's bit for bit (the
+ * same per-wave code runs). */
+
+typedef struct fcfs_server_* fcfs_server_t;
+
+typedef struct {
+  int p, q;              /* scale factor (both axes, half-pixel grid) */
+  fcfs_method method;    /* FCFS_NEAREST, FCFS_BILINEAR or FCFS_BICUBIC */
+  fcfs_pad pad;
+  fcfs_dtype dtype;      /* FCFS_F32 or FCFS_BF16 */
+  int64_t n, c, h, w;
+  const void* x;         /* device input owned by the caller (valid until done), or NULL:
+                            the server generates it in its arena from `seed` (element i of
+                            the NCHW tensor = top 24 bits of splitmix64(seed, i) / 2^24,
+                            rounded to the storage type) */
+  uint64_t seed;
+  void* y;               /* device output owned by the caller, or NULL: allocated in the
+                            server arena, valid until fcfs_release */
+} fcfs_request;
+
+typedef struct {
+  fcfs_status status;    /* FCFS_OK, or the request's own failure (FCFS_E_NOMEM: larger
+                            than the memory budget; FCFS_E_DEVICE: its batch failed) */
+  void* y;               /* device output */
+  int64_t h_out, w_out;
+  double t_arrive_us, t_start_us, t_done_us;   /* since server creation */
+} fcfs_result;
+
+/* Create a server on HIP device `device` with a device memory budget (the
+ * arena holding generated inputs and server-owned outputs; allocated once,
+ * here) and at most `max_slots` admitted, unfinished requests.
+ * Errors: FCFS_E_INVAL, FCFS_E_NOMEM (arena), FCFS_E_DEVICE (no such device). */
+fcfs_status fcfs_server_create(int device, size_t mem_budget_bytes, int max_slots, fcfs_server_t* out);
+
+/* Queue a request; *ticket identifies it. Argument errors are returned here
+ * and queue nothing. FCFS_E_AGAIN when the pending queue is full. */
+fcfs_status fcfs_submit(fcfs_server_t server, const fcfs_request* req, uint64_t* ticket);
+
+/* FCFS_OK with *out filled when the request is finished (out->status holds
+ * its outcome), FCFS_E_PENDING before that, FCFS_E_INVAL for an unknown
+ * ticket. */
+fcfs_status fcfs_poll(fcfs_server_t server, uint64_t ticket, fcfs_result* out);
+
+/* As fcfs_poll, blocking up to timeout_us microseconds (negative: no limit). */
+fcfs_status fcfs_wait(fcfs_server_t server, uint64_t ticket, int64_t timeout_us, fcfs_result* out);
+
+/* Forget a finished request and free its server-owned output.
+ * FCFS_E_PENDING if it is not finished. */
+fcfs_status fcfs_release(fcfs_server_t server, uint64_t ticket);
+
+/* Latency percentiles (arrival to completion) over finished requests,
+ * finished requests per second and algorithmic GB/s over the span from the
+ * first arrival to the last completion. Any pointer may be NULL. */
+fcfs_status fcfs_server_stats(fcfs_server_t server, double* p50_us, double* p99_us, double* req_per_s,
+                              double* gbps);
+
+/* Test hooks (they force failure paths without faulting anything): hook 1
+ * makes the next `value` requests at the head of the queue fail with
+ * FCFS_E_NOMEM as if the arena had refused them; hook 2 makes the next
+ * `value` batches fail as if their launch had failed (nothing is launched). */
+fcfs_status fcfs_server_debug(fcfs_server_t server, int hook, int64_t value);
+
+/* Finish every admitted request, stop the threads and free everything. Tickets
+ * still pending are completed with FCFS_E_CANCELLED. */
+fcfs_status fcfs_server_destroy(fcfs_server_t server);
+
 /* Static text for a status code. */
 const char* fcfs_status_string(fcfs_status status);
 

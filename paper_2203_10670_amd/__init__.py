@@ -22,6 +22,9 @@ __all__ = [
     "fcfs_output_size",
     "fcfs_forward", "fcfs_forward_config", "fcfs_backward_workspace", "fcfs_backward", "fcfs_status_string",
     "fcfs_version", "Plan", "resize", "FCFSFunction",
+    "fcfs_request", "fcfs_result", "fcfs_server_create", "fcfs_submit", "fcfs_poll", "fcfs_wait",
+    "fcfs_release", "fcfs_server_stats", "fcfs_server_debug", "fcfs_server_destroy", "Server",
+    "device_view",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,6 +75,29 @@ _sig("fcfs_forward_config", [_P, _I, _I64, _I64, _I64, _I64, ctypes.POINTER(_I),
                              ctypes.POINTER(_I), ctypes.POINTER(_I64)])
 _sig("fcfs_backward_workspace", [_P, _I, _I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)])
 _sig("fcfs_backward", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P])
+
+
+class fcfs_request(ctypes.Structure):
+    _fields_ = [("p", _I), ("q", _I), ("method", _I), ("pad", _I), ("dtype", _I),
+                ("n", _I64), ("c", _I64), ("h", _I64), ("w", _I64),
+                ("x", _P), ("seed", ctypes.c_uint64), ("y", _P)]
+
+
+class fcfs_result(ctypes.Structure):
+    _fields_ = [("status", _I), ("y", _P), ("h_out", _I64), ("w_out", _I64),
+                ("t_arrive_us", ctypes.c_double), ("t_start_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_sig("fcfs_server_create", [_I, _SZ, _I, _PP])
+_sig("fcfs_submit", [_P, ctypes.POINTER(fcfs_request), ctypes.POINTER(ctypes.c_uint64)])
+_sig("fcfs_poll", [_P, ctypes.c_uint64, ctypes.POINTER(fcfs_result)])
+_sig("fcfs_wait", [_P, ctypes.c_uint64, _I64, ctypes.POINTER(fcfs_result)])
+_sig("fcfs_release", [_P, ctypes.c_uint64])
+_sig("fcfs_server_stats", [_P, _D, _D, _D, _D])
+_sig("fcfs_server_debug", [_P, _I, _I64])
+_sig("fcfs_server_destroy", [_P])
 _sig("fcfs_status_string", [_I], ctypes.c_char_p)
 _sig("fcfs_version", [], _I)
 
@@ -151,6 +177,119 @@ def fcfs_backward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, 
                   ws_ptr, ws_bytes, stream) -> int:
     return lib.fcfs_backward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, dx_ptr,
                              dw_ptr, ws_ptr, ws_bytes, stream)
+
+
+def fcfs_server_create(device: int, mem_budget_bytes: int, max_slots: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.fcfs_server_create(device, mem_budget_bytes, max_slots, ctypes.byref(h)), "fcfs_server_create")
+    return h.value
+
+
+def fcfs_submit(server: int, req: fcfs_request):
+    """Returns (status, ticket)."""
+    t = ctypes.c_uint64()
+    st = lib.fcfs_submit(server, ctypes.byref(req), ctypes.byref(t))
+    return st, t.value
+
+
+def fcfs_poll(server: int, ticket: int):
+    r = fcfs_result()
+    st = lib.fcfs_poll(server, ticket, ctypes.byref(r))
+    return st, r
+
+
+def fcfs_wait(server: int, ticket: int, timeout_us: int = -1):
+    r = fcfs_result()
+    st = lib.fcfs_wait(server, ticket, timeout_us, ctypes.byref(r))
+    return st, r
+
+
+def fcfs_release(server: int, ticket: int) -> int:
+    return lib.fcfs_release(server, ticket)
+
+
+def fcfs_server_stats(server: int):
+    """(p50_us, p99_us, req_per_s, gbps)."""
+    v = [ctypes.c_double() for _ in range(4)]
+    _check(lib.fcfs_server_stats(server, *[ctypes.byref(x) for x in v]), "fcfs_server_stats")
+    return tuple(x.value for x in v)
+
+
+def fcfs_server_debug(server: int, hook: int, value: int) -> int:
+    return lib.fcfs_server_debug(server, hook, value)
+
+
+def fcfs_server_destroy(server: int) -> None:
+    _check(lib.fcfs_server_destroy(server), "fcfs_server_destroy")
+
+
+class Server:
+    """Owns an fcfs serving loop on one device."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 64 << 30, max_slots: int = 256):
+        self.handle = fcfs_server_create(device, mem_budget_bytes, max_slots)
+
+    def submit(self, p, q, method="bilinear", pad="replicate", dtype="f32", shape=(1, 1, 1, 1), x=None,
+               seed=0, y=None):
+        """Queue a request; x / y are device tensors (or None: generated input
+        from ``seed`` / server-owned output). Returns the ticket."""
+        n, c, h, w = shape
+        req = fcfs_request(p, q, METHODS[method], PADS[pad], DTYPES[dtype], n, c, h, w,
+                           None if x is None else _dev_ptr(x), seed, None if y is None else _dev_ptr(y))
+        st, t = fcfs_submit(self.handle, req)
+        _check(st, "fcfs_submit")
+        return t
+
+    def wait(self, ticket, timeout_us=-1):
+        st, r = fcfs_wait(self.handle, ticket, timeout_us)
+        _check(st, "fcfs_wait")
+        return r
+
+    def release(self, ticket):
+        _check(fcfs_release(self.handle, ticket), "fcfs_release")
+
+    def stats(self):
+        return fcfs_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fcfs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def device_view(ptr: int, shape, dtype: str, device=None):
+    """A torch tensor over device memory owned by the library (a server
+    output); valid until the ticket is released. The memory is copied."""
+    torch = _torch()
+    td = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    n = 1
+    for d in shape:
+        n *= d
+    out = torch.empty(shape, dtype=td, device=device or "cuda")
+    if n:
+        _check(0 if lib_copy(out.data_ptr(), ptr, n * out.element_size()) == 0 else E_DEVICE, "copy")
+    return out
+
+
+def lib_copy(dst: int, src: int, nbytes: int) -> int:
+    """Device-to-device copy through the HIP runtime (used to read server outputs)."""
+    hip = _hip()
+    return hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 3)
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [_P, _P, _SZ, _I]
+        _hip_lib.hipMemcpy.restype = _I
+    return _hip_lib
 
 
 # ------------------------------------------------------------------ torch layer

@@ -125,8 +125,23 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
   return FCFS_OK;
 }
 
+static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
+                                bool batch, FwdGeom* g);
+
 fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
                               FwdGeom* g) {
+  return forward_geom(plan, planes, h, w, ho, wo, false, g);
+}
+
+// The batched kernel carries the instances with 4 or 1 column groups per lane
+// and 8 staged slots.
+fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
+                                    FwdGeom* g) {
+  return forward_geom(plan, planes, h, w, ho, wo, true, g);
+}
+
+static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
+                                bool batch, FwdGeom* g) {
   (void)h;
   (void)w;
   const AxisTable& aw = plan->aw;
@@ -139,12 +154,12 @@ fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int
 #define FCFS_FWD_MAX_KC 4
 #endif
   int kc = learned ? 1 : FCFS_FWD_MAX_KC;
-  while (kc > 1 && (seg(64 * kc) > 512 || wo <= 64 * (kc / 2))) kc /= 2;
+  while (kc > 1 && (seg(64 * kc) > 512 || wo <= 64 * (kc / 2))) kc = batch ? 1 : kc / 2;
   int tw = 64 * kc;
   while (tw > 1 && seg(tw) > 512) tw /= 2;
   if (seg(tw) > 512) return FCFS_E_UNSUPPORTED;
   const int need = seg(tw);
-  g->slots = need <= 128 ? 2 : (need <= 256 ? 4 : 8);
+  g->slots = batch ? 8 : (need <= 128 ? 2 : (need <= 256 ? 4 : 8));
   g->kc = kc;
   g->tw = tw;
   g->strips = (wo + tw - 1) / tw;

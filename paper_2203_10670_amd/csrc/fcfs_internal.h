@@ -98,6 +98,41 @@ struct MixArgs {
   AxisTable th, tw_tab;
 };
 
+// ---------------------------------------------------------------- serving
+// One request of a batched launch (in device memory).
+struct BatchDesc {
+  FwdArgs args;
+  int variant;      // forward instance: dtype (0 f32, 1 bf16) * 6 + tap index (0: 1, 1: 2, 2: 4) * 2 + (kc == 4 ? 0 : 1)
+  int pad_[3];
+};
+struct BatchArgs {
+  const BatchDesc* desc;
+  const int64_t* wave_start;   // [nreq + 1] prefix of waves per request
+  int nreq;
+  int64_t total_waves;
+};
+// A request whose input the server generates.
+struct GenDesc {
+  void* x;
+  int64_t count;     // elements
+  uint64_t seed;
+  int dtype;
+  int pad_;
+};
+struct GenArgs {
+  const GenDesc* desc;
+  const int64_t* block_start;  // [ngen + 1] prefix of blocks per request
+  int ngen;
+  int64_t total_blocks;
+};
+constexpr int kGenPerBlock = 256 * 16;   // elements per generator block
+
+fcfs_status launch_forward_batch(const BatchArgs& b, hipStream_t stream);
+fcfs_status launch_generate(const GenArgs& g, hipStream_t stream);
+// Launch geometry for a batched request (restricted to the batched kernel's instances).
+fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
+                                    FwdGeom* g);
+
 // Channel-mixing launchers (mix4.hip); dtype FCFS_BF16 or FCFS_F16.
 fcfs_status launch_mix4(int dtype, const MixArgs& a, hipStream_t stream);
 

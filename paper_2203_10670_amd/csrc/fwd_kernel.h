@@ -111,27 +111,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The per-wave work of the forward: wave `wid` of the launch described by `a`
+// (a may live in the kernel-argument segment or in device memory).
 template <int DT, int T, int KC, int L, bool LEARNED>
-__global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
+__device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslot, int lane, float* smem) {
   using S = Store<DT>;
   using TS = typename S::T;
-  extern __shared__ float smem[];
-
-  const int lane = threadIdx.x & 63;
-  const int wslot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int64_t blk = blockIdx.x;
-  if (FCFS_FWD_XCD_SWIZZLE) {
-    // Workgroup b runs on XCD b % 8. Give each XCD a contiguous range of the
-    // logical order, so that neighbouring strips and bands (which share
-    // halo cache lines) meet in the same L2.
-    const int64_t nb = gridDim.x;
-    const int64_t per = nb / kXcds, rem = nb % kXcds;
-    const int64_t x = blk % kXcds, i = blk / kXcds;
-    blk = x * per + min(x, rem) + i;
-  }
-  const int64_t wid = blk * kWaves + wslot;
-  if (wid >= a.waves) return;
-
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
 
@@ -305,6 +290,26 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
       rho = (rho + 1 == TH.q) ? 0 : rho + 1;
     }
   }
+}
+
+template <int DT, int T, int KC, int L, bool LEARNED>
+__global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
+  extern __shared__ float smem[];
+  const int lane = threadIdx.x & 63;
+  const int wslot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t blk = blockIdx.x;
+  if (FCFS_FWD_XCD_SWIZZLE) {
+    // Workgroup b runs on XCD b % 8. Give each XCD a contiguous range of the
+    // logical order, so that neighbouring strips and bands (which share
+    // halo cache lines) meet in the same L2.
+    const int64_t nb = gridDim.x;
+    const int64_t per = nb / kXcds, rem = nb % kXcds;
+    const int64_t x = blk % kXcds, i = blk / kXcds;
+    blk = x * per + min(x, rem) + i;
+  }
+  const int64_t wid = blk * kWaves + wslot;
+  if (wid >= a.waves) return;
+  fwd_wave<DT, T, KC, L, LEARNED>(a, wid, wslot, lane, smem);
 }
 
 template <int DT, int T, int KC, bool LEARNED>

@@ -1,0 +1,595 @@
+// Serving loop of libfcfs: continuous batching of rescale requests on one GPU.
+//
+// Threads. Clients call fcfs_submit from any thread (requests go to a FIFO).
+// The scheduler thread admits requests from the head of the FIFO while
+// request slots and the device arena allow, then launches one batch: a
+// generator launch for the admitted requests whose input it must create, the
+// descriptor upload and one batched forward launch, on one of two streams in
+// turn. The completion thread waits for each batch's event in launch order,
+// timestamps its requests and frees their arena inputs and slots.
+//
+// Memory. The arena is one device allocation made at creation; a first-fit
+// free list (offsets, 256-byte granules, neighbours merged on free) hands out
+// generated inputs and server-owned outputs. A request that cannot fit even
+// in an empty arena fails alone with FCFS_E_NOMEM; one that does not fit now
+// waits at the head of the FIFO until completions free space.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "fcfs_internal.h"
+
+namespace fcfs {
+namespace {
+
+constexpr size_t kGranule = 256;
+constexpr size_t kMaxPending = 1 << 16;
+
+size_t round_up(size_t b) { return (b + kGranule - 1) / kGranule * kGranule; }
+
+class Arena {
+ public:
+  void init(size_t bytes) {
+    size_ = bytes;
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  // Returns the offset, or SIZE_MAX when no free block is large enough.
+  size_t alloc(size_t bytes) {
+    bytes = round_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, rest = it->second - bytes;
+      free_.erase(it);
+      if (rest) free_[off + bytes] = rest;
+      used_ += bytes;
+      return off;
+    }
+    return SIZE_MAX;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = round_up(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+
+ private:
+  size_t size_ = 0;
+  size_t used_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> bytes
+};
+
+enum TicketState { kPending = 0, kAdmitted = 1, kDone = 2 };
+
+struct Ticket {
+  fcfs_request req;
+  int state = kPending;
+  fcfs_status status = FCFS_OK;
+  fcfs_plan_t plan = nullptr;
+  int64_t ho = 0, wo = 0;
+  size_t x_bytes = 0, y_bytes = 0;
+  size_t x_off = SIZE_MAX, y_off = SIZE_MAX;   // arena offsets when server-owned
+  void* x = nullptr;
+  void* y = nullptr;
+  uint64_t alg_bytes = 0;                      // input rows read + output
+  double t_arrive = 0, t_start = 0, t_done = 0;
+};
+
+struct Batch {
+  std::vector<uint64_t> tickets;
+  hipEvent_t done = nullptr;
+  int stream = 0;
+  bool failed = false;
+};
+
+// Host staging and device copy of one stream's batch descriptors.
+struct StreamBufs {
+  hipStream_t stream = nullptr;
+  hipEvent_t last = nullptr;       // event of the last batch launched on this stream
+  bool busy = false;
+  BatchDesc* h_desc = nullptr;     // pinned
+  int64_t* h_wave = nullptr;
+  GenDesc* h_gen = nullptr;
+  int64_t* h_gblk = nullptr;
+  BatchDesc* d_desc = nullptr;
+  int64_t* d_wave = nullptr;
+  GenDesc* d_gen = nullptr;
+  int64_t* d_gblk = nullptr;
+};
+
+}  // namespace
+}  // namespace fcfs
+
+struct fcfs_server_ {
+  int device = 0;
+  int max_slots = 0;
+  char* arena_base = nullptr;
+  fcfs::Arena arena;
+  fcfs::StreamBufs sb[2];
+  int next_stream = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_sched;    // scheduler: work arrived / space freed / stop
+  std::condition_variable cv_done;     // waiters: a request finished
+  std::condition_variable cv_batch;    // completion thread: a batch was launched
+  std::deque<uint64_t> fifo;           // pending tickets in arrival order
+  std::unordered_map<uint64_t, fcfs::Ticket> tickets;
+  std::deque<fcfs::Batch> inflight;
+  std::map<uint64_t, fcfs_plan_t> plans;   // plan cache by (p, q, method, pad)
+  int slots_used = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int fail_allocs = 0;
+  int fail_batches = 0;
+  uint64_t frees = 0;                  // completions and releases: arena space may have come back
+
+  // statistics of finished requests
+  std::vector<double> latencies;
+  double first_arrive = -1, last_done = 0;
+  double done_bytes = 0;
+  int64_t done_count = 0;
+
+  std::chrono::steady_clock::time_point t0;
+  std::thread scheduler, completer;
+
+  double now_us() const {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace fcfs {
+namespace {
+
+uint64_t plan_key(const fcfs_request& r) {
+  return ((uint64_t)r.p << 40) | ((uint64_t)r.q << 20) | ((uint64_t)r.method << 8) | (uint64_t)r.pad;
+}
+
+// Input rows some tap reads (height axis) times the row bytes, plus the output.
+uint64_t algorithmic_bytes(const fcfs_plan_* pl, const Ticket& t, size_t es) {
+  const AxisTable& a = pl->ah;
+  const int64_t h = t.req.h, cells = t.ho / a.p;
+  std::vector<char> hit((size_t)h, 0);
+  for (int64_t m = 0; m < cells; ++m)
+    for (int j = 0; j < a.p; ++j)
+      for (int k = 0; k < a.T; ++k) {
+        const int64_t r = a.q * m + a.off[j] + k;
+        if (r >= 0 && r < h) hit[(size_t)r] = 1;
+      }
+  int64_t rows = 0;
+  for (char c : hit) rows += c;
+  return (uint64_t)(t.req.n * t.req.c) * (uint64_t)(rows * t.req.w + t.ho * t.wo) * es;
+}
+
+size_t elem_size(int dtype) { return dtype == FCFS_F32 ? 4 : 2; }
+
+int variant_of(int dtype, int taps, int kc) {
+  const int ti = taps == 1 ? 0 : (taps == 2 ? 1 : 2);
+  return (dtype == FCFS_BF16 ? 6 : 0) + ti * 2 + (kc == 4 ? 0 : 1);
+}
+
+// Marks a ticket finished (lock held).
+void finish(fcfs_server_* s, Ticket& t, fcfs_status st, double when) {
+  t.status = st;
+  t.state = kDone;
+  t.t_done = when;
+  if (t.x_off != SIZE_MAX) {
+    s->arena.release(t.x_off, t.x_bytes);
+    t.x_off = SIZE_MAX;
+    t.x = nullptr;
+  }
+  if (st != FCFS_OK && t.y_off != SIZE_MAX) {
+    s->arena.release(t.y_off, t.y_bytes);
+    t.y_off = SIZE_MAX;
+    t.y = nullptr;
+  }
+  if (st == FCFS_OK) {
+    s->latencies.push_back(t.t_done - t.t_arrive);
+    if (s->first_arrive < 0 || t.t_arrive < s->first_arrive) s->first_arrive = t.t_arrive;
+    s->last_done = std::max(s->last_done, t.t_done);
+    s->done_bytes += (double)t.alg_bytes;
+    ++s->done_count;
+  }
+}
+
+// Arena space for one request (lock held). Returns false when it does not fit now.
+bool reserve(fcfs_server_* s, Ticket& t) {
+  size_t xo = SIZE_MAX, yo = SIZE_MAX;
+  if (!t.req.x) {
+    xo = s->arena.alloc(t.x_bytes);
+    if (xo == SIZE_MAX) return false;
+  }
+  if (!t.req.y) {
+    yo = s->arena.alloc(t.y_bytes);
+    if (yo == SIZE_MAX) {
+      if (xo != SIZE_MAX) s->arena.release(xo, t.x_bytes);
+      return false;
+    }
+  }
+  t.x_off = xo;
+  t.y_off = yo;
+  t.x = t.req.x ? const_cast<void*>(t.req.x) : s->arena_base + xo;
+  t.y = t.req.y ? t.req.y : s->arena_base + yo;
+  return true;
+}
+
+void scheduler_loop(fcfs_server_* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    StreamBufs& sb = s->sb[s->next_stream];
+    s->cv_sched.wait(lk, [&] {
+      return s->stop || (!s->fifo.empty() && s->slots_used < s->max_slots && !sb.busy);
+    });
+    if (s->stop && s->fifo.empty()) break;
+    if (s->stop) {
+      // cancel whatever never started
+      const double now = s->now_us();
+      while (!s->fifo.empty()) {
+        Ticket& t = s->tickets[s->fifo.front()];
+        s->fifo.pop_front();
+        finish(s, t, FCFS_E_CANCELLED, now);
+      }
+      s->cv_done.notify_all();
+      break;
+    }
+    // admit from the head of the FIFO
+    Batch batch;
+    batch.stream = s->next_stream;
+    int ngen = 0;
+    int64_t waves = 0, gblocks = 0;
+    const double now = s->now_us();
+    while (!s->fifo.empty() && s->slots_used < s->max_slots) {
+      const uint64_t id = s->fifo.front();
+      Ticket& t = s->tickets[id];
+      const size_t need = (t.req.x ? 0 : round_up(t.x_bytes)) + (t.req.y ? 0 : round_up(t.y_bytes));
+      if (need > s->arena.size() || s->fail_allocs > 0) {   // can never fit (or forced): fail it alone
+        if (need <= s->arena.size()) --s->fail_allocs;
+        s->fifo.pop_front();
+        finish(s, t, FCFS_E_NOMEM, now);
+        s->cv_done.notify_all();
+        continue;
+      }
+      if (!reserve(s, t)) break;   // wait until completions or releases free space
+      s->fifo.pop_front();
+      t.state = kAdmitted;
+      t.t_start = now;
+      ++s->slots_used;
+      // descriptor
+      const int i = (int)batch.tickets.size();
+      BatchDesc& d = sb.h_desc[i];
+      std::memset(&d, 0, sizeof(d));
+      FwdArgs& a = d.args;
+      a.x = t.x;
+      a.y = t.y;
+      a.weight = nullptr;
+      a.planes = t.req.n * t.req.c;
+      a.C = (int)t.req.c;
+      a.H = (int)t.req.h;
+      a.W = (int)t.req.w;
+      a.Ho = (int)t.ho;
+      a.Wo = (int)t.wo;
+      a.Mh = (int)(t.ho / t.plan->ah.p);
+      a.pad = t.plan->pad;
+      a.th = t.plan->ah;
+      a.tw_tab = t.plan->aw;
+      FwdGeom g;
+      plan_forward_geom_batch(t.plan, a.planes, a.H, a.W, a.Ho, a.Wo, &g);
+      a.tw = g.tw;
+      a.strips = g.strips;
+      a.band_cells = g.band_cells;
+      a.bands = g.bands;
+      a.waves = g.waves;
+      d.variant = variant_of(t.req.dtype, t.plan->ah.T, g.kc);
+      sb.h_wave[i] = waves;
+      waves += g.waves;
+      if (!t.req.x) {
+        GenDesc& gd = sb.h_gen[ngen];
+        gd.x = t.x;
+        gd.count = t.req.n * t.req.c * t.req.h * t.req.w;
+        gd.seed = t.req.seed;
+        gd.dtype = t.req.dtype;
+        sb.h_gblk[ngen] = gblocks;
+        gblocks += (gd.count + kGenPerBlock - 1) / kGenPerBlock;
+        ++ngen;
+      }
+      batch.tickets.push_back(id);
+    }
+    if (batch.tickets.empty()) {
+      // the head request waits for arena space: sleep until a completion or a
+      // release returns some
+      const uint64_t seen = s->frees;
+      s->cv_sched.wait(lk, [&] { return s->stop || s->frees != seen || s->fifo.empty(); });
+      continue;
+    }
+    const int nreq = (int)batch.tickets.size();
+    sb.h_wave[nreq] = waves;
+    sb.h_gblk[ngen] = gblocks;
+    bool fail = false;
+    if (s->fail_batches > 0) {
+      --s->fail_batches;
+      fail = true;
+    }
+    // launch (outside the lock: the upload and launches do not touch shared state)
+    sb.busy = true;
+    s->next_stream ^= 1;
+    lk.unlock();
+    hipStream_t st = sb.stream;
+    bool ok = !fail;
+    if (ok && ngen > 0) {
+      ok = hipMemcpyAsync(sb.d_gen, sb.h_gen, sizeof(GenDesc) * ngen, hipMemcpyHostToDevice, st) == hipSuccess &&
+           hipMemcpyAsync(sb.d_gblk, sb.h_gblk, sizeof(int64_t) * (ngen + 1), hipMemcpyHostToDevice, st) ==
+               hipSuccess;
+      GenArgs ga{sb.d_gen, sb.d_gblk, ngen, gblocks};
+      ok = ok && launch_generate(ga, st) == FCFS_OK;
+    }
+    if (ok) {
+      ok = hipMemcpyAsync(sb.d_desc, sb.h_desc, sizeof(BatchDesc) * nreq, hipMemcpyHostToDevice, st) ==
+               hipSuccess &&
+           hipMemcpyAsync(sb.d_wave, sb.h_wave, sizeof(int64_t) * (nreq + 1), hipMemcpyHostToDevice, st) ==
+               hipSuccess;
+      BatchArgs ba{sb.d_desc, sb.d_wave, nreq, waves};
+      ok = ok && launch_forward_batch(ba, st) == FCFS_OK;
+    }
+    batch.failed = !ok;
+    batch.done = sb.last;
+    hipEventRecord(sb.last, st);
+    lk.lock();
+    s->inflight.push_back(std::move(batch));
+    s->cv_batch.notify_all();
+  }
+}
+
+void completion_loop(fcfs_server_* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_batch.wait(lk, [&] { return !s->inflight.empty() || (s->stop && s->inflight.empty()); });
+    if (s->inflight.empty()) {
+      if (s->stop) break;
+      continue;
+    }
+    Batch& b = s->inflight.front();
+    hipEvent_t ev = b.done;
+    lk.unlock();
+    const bool dev_ok = hipEventSynchronize(ev) == hipSuccess;
+    lk.lock();
+    Batch done = std::move(s->inflight.front());
+    s->inflight.pop_front();
+    const double when = s->now_us();
+    const fcfs_status st = (done.failed || !dev_ok) ? FCFS_E_DEVICE : FCFS_OK;
+    for (uint64_t id : done.tickets) {
+      Ticket& t = s->tickets[id];
+      finish(s, t, st, when);
+      --s->slots_used;
+    }
+    s->sb[done.stream].busy = false;
+    ++s->frees;
+    s->cv_done.notify_all();
+    s->cv_sched.notify_all();
+  }
+}
+
+void free_stream_bufs(StreamBufs& b) {
+  if (b.h_desc) hipHostFree(b.h_desc);
+  if (b.h_wave) hipHostFree(b.h_wave);
+  if (b.h_gen) hipHostFree(b.h_gen);
+  if (b.h_gblk) hipHostFree(b.h_gblk);
+  if (b.d_desc) hipFree(b.d_desc);
+  if (b.d_wave) hipFree(b.d_wave);
+  if (b.d_gen) hipFree(b.d_gen);
+  if (b.d_gblk) hipFree(b.d_gblk);
+  if (b.last) hipEventDestroy(b.last);
+  if (b.stream) hipStreamDestroy(b.stream);
+  b = StreamBufs();
+}
+
+fcfs_status fill_result(const Ticket& t, fcfs_result* out) {
+  if (out) {
+    out->status = t.status;
+    out->y = t.status == FCFS_OK ? t.y : nullptr;
+    out->h_out = t.ho;
+    out->w_out = t.wo;
+    out->t_arrive_us = t.t_arrive;
+    out->t_start_us = t.t_start;
+    out->t_done_us = t.t_done;
+  }
+  return FCFS_OK;
+}
+
+}  // namespace
+}  // namespace fcfs
+
+using namespace fcfs;
+
+extern "C" {
+
+fcfs_status fcfs_server_create(int device, size_t mem_budget_bytes, int max_slots, fcfs_server_t* out) {
+  if (!out || max_slots < 1 || max_slots > 4096 || mem_budget_bytes < kGranule) return FCFS_E_INVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FCFS_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FCFS_E_DEVICE;
+  fcfs_server_* s = new (std::nothrow) fcfs_server_();
+  if (!s) return FCFS_E_NOMEM;
+  s->device = device;
+  s->max_slots = max_slots;
+  s->t0 = std::chrono::steady_clock::now();
+  const size_t budget = mem_budget_bytes / kGranule * kGranule;
+  if (hipMalloc(reinterpret_cast<void**>(&s->arena_base), budget) != hipSuccess) {
+    delete s;
+    return FCFS_E_NOMEM;
+  }
+  s->arena.init(budget);
+  bool ok = true;
+  for (auto& b : s->sb) {
+    ok = ok && hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b.last, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b.h_desc), sizeof(BatchDesc) * max_slots) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b.h_wave), sizeof(int64_t) * (max_slots + 1)) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b.h_gen), sizeof(GenDesc) * max_slots) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b.h_gblk), sizeof(int64_t) * (max_slots + 1)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b.d_desc), sizeof(BatchDesc) * max_slots) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b.d_wave), sizeof(int64_t) * (max_slots + 1)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b.d_gen), sizeof(GenDesc) * max_slots) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b.d_gblk), sizeof(int64_t) * (max_slots + 1)) == hipSuccess;
+  }
+  if (!ok) {
+    for (auto& b : s->sb) free_stream_bufs(b);
+    hipFree(s->arena_base);
+    delete s;
+    return FCFS_E_NOMEM;
+  }
+  s->scheduler = std::thread(scheduler_loop, s);
+  s->completer = std::thread(completion_loop, s);
+  *out = s;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_submit(fcfs_server_t s, const fcfs_request* r, uint64_t* ticket) {
+  if (!s || !r || !ticket) return FCFS_E_INVAL;
+  if (r->method != FCFS_NEAREST && r->method != FCFS_BILINEAR && r->method != FCFS_BICUBIC) return FCFS_E_INVAL;
+  if (r->dtype != FCFS_F32 && r->dtype != FCFS_BF16) return FCFS_E_INVAL;
+  if (r->n < 1 || r->c < 1 || r->h < 1 || r->w < 1) return FCFS_E_INVAL;
+  Ticket t;
+  t.req = *r;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->stop) return FCFS_E_INVAL;
+  if (s->fifo.size() >= kMaxPending) return FCFS_E_AGAIN;
+  const uint64_t key = plan_key(*r);
+  auto it = s->plans.find(key);
+  if (it == s->plans.end()) {
+    fcfs_plan_t pl = nullptr;
+    fcfs_status st = fcfs_plan(r->p, r->q, r->method, r->pad, &pl);
+    if (st != FCFS_OK) return st;
+    it = s->plans.emplace(key, pl).first;
+  }
+  t.plan = it->second;
+  fcfs_output_size(t.plan, r->h, r->w, &t.ho, &t.wo);
+  const int64_t in_plane = r->h * r->w, out_plane = t.ho * t.wo;
+  if (in_plane >= (1LL << 31) || out_plane >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
+  const size_t es = elem_size(r->dtype);
+  t.x_bytes = (size_t)(r->n * r->c * in_plane) * es;
+  t.y_bytes = (size_t)(r->n * r->c * out_plane) * es;
+  t.alg_bytes = algorithmic_bytes(t.plan, t, es);
+  t.t_arrive = s->now_us();
+  const uint64_t id = s->next_ticket++;
+  s->tickets.emplace(id, std::move(t));
+  s->fifo.push_back(id);
+  *ticket = id;
+  s->cv_sched.notify_all();
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_poll(fcfs_server_t s, uint64_t ticket, fcfs_result* out) {
+  if (!s) return FCFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return FCFS_E_INVAL;
+  if (it->second.state != kDone) return FCFS_E_PENDING;
+  return fill_result(it->second, out);
+}
+
+fcfs_status fcfs_wait(fcfs_server_t s, uint64_t ticket, int64_t timeout_us, fcfs_result* out) {
+  if (!s) return FCFS_E_INVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto done = [&] {
+    auto it = s->tickets.find(ticket);
+    return it == s->tickets.end() || it->second.state == kDone;
+  };
+  if (timeout_us < 0) s->cv_done.wait(lk, done);
+  else s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return FCFS_E_INVAL;
+  if (it->second.state != kDone) return FCFS_E_PENDING;
+  return fill_result(it->second, out);
+}
+
+fcfs_status fcfs_release(fcfs_server_t s, uint64_t ticket) {
+  if (!s) return FCFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return FCFS_E_INVAL;
+  if (it->second.state != kDone) return FCFS_E_PENDING;
+  if (it->second.y_off != SIZE_MAX) s->arena.release(it->second.y_off, it->second.y_bytes);
+  s->tickets.erase(it);
+  ++s->frees;
+  s->cv_sched.notify_all();
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_server_stats(fcfs_server_t s, double* p50_us, double* p99_us, double* req_per_s, double* gbps) {
+  if (!s) return FCFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::vector<double> v = s->latencies;
+  auto pct = [&](double f) -> double {
+    if (v.empty()) return 0.0;
+    const size_t k = std::min(v.size() - 1, (size_t)(f * (double)(v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + k, v.end());
+    return v[k];
+  };
+  if (p50_us) *p50_us = pct(0.50);
+  if (p99_us) *p99_us = pct(0.99);
+  const double span = s->last_done - s->first_arrive;
+  if (req_per_s) *req_per_s = span > 0 ? s->done_count / (span * 1e-6) : 0.0;
+  if (gbps) *gbps = span > 0 ? s->done_bytes / (span * 1e-6) / 1e9 : 0.0;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_server_debug(fcfs_server_t s, int hook, int64_t value) {
+  if (!s || value < 0) return FCFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (hook == 1) s->fail_allocs = (int)value;
+  else if (hook == 2) s->fail_batches = (int)value;
+  else return FCFS_E_INVAL;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_server_destroy(fcfs_server_t s) {
+  if (!s) return FCFS_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_sched.notify_all();
+    s->cv_batch.notify_all();
+  }
+  s->scheduler.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_batch.notify_all();
+  }
+  s->completer.join();
+  hipSetDevice(s->device);
+  for (auto& b : s->sb) free_stream_bufs(b);
+  hipFree(s->arena_base);
+  for (auto& kv : s->plans) fcfs_plan_destroy(kv.second);
+  delete s;
+  return FCFS_OK;
+}
+
+}  // extern "C"

@@ -102,3 +102,16 @@ def oracle_crop(x, p, q, method, pad, mh, mw, weight=None, cout=None):
     # taps stay inside the crop are returned, and those do not see that edge
     a, b = r0 // qr, c0 // qr
     return full[:, :, pr * (mh[0] - a): pr * (mh[1] - a), pr * (mw[0] - b): pr * (mw[1] - b)]
+
+
+def splitmix64_uniform(seed, count):
+    """The serving loop's generated input, element i: the top 24 bits of
+    splitmix64(seed + (i + 1) * 0x9E3779B97F4A7C15) over 2^24 (the published
+    SplitMix64 finaliser), as float32."""
+    with np.errstate(over="ignore"):
+        i = np.arange(count, dtype=np.uint64)
+        z = np.uint64(seed) + (i + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return ((z >> np.uint64(40)).astype(np.float64) / 16777216.0).astype(np.float32)

@@ -114,3 +114,28 @@ def test_anisotropic_plan():
     pl = fc.Plan(1, 1, "bicubic", "reflect", pw=3, qw=2)
     assert pl.taps == 4
     assert fc.fcfs_plan_taps(pl.handle, 0, 0)[1] == [0.0, 1.0, 0.0, 0.0]
+
+
+def test_request_structs_match_header(tmp_path):
+    # the ctypes mirrors of fcfs_request / fcfs_result have the C layout
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fcfs.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fcfs_request), sizeof(fcfs_result),'
+                   'offsetof(fcfs_request, n), offsetof(fcfs_request, seed), offsetof(fcfs_request, y),'
+                   'offsetof(fcfs_result, t_done_us));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    want = [ctypes.sizeof(fc.fcfs_request), ctypes.sizeof(fc.fcfs_result), fc.fcfs_request.n.offset,
+            fc.fcfs_request.seed.offset, fc.fcfs_request.y.offset, fc.fcfs_result.t_done_us.offset]
+    assert [int(v) for v in got] == want
+
+
+def test_server_needs_a_device():
+    # no GPU here: creation reports a device error and nothing else happens
+    with pytest.raises(fc.FcfsError) as e:
+        fc.Server(0, 1 << 20, 4)
+    assert e.value.status in (fc.E_DEVICE, fc.E_NOMEM)
+    h = ctypes.c_void_p()
+    assert fc.lib.fcfs_server_create(0, 1 << 20, 0, ctypes.byref(h)) == fc.E_INVAL
