@@ -190,6 +190,52 @@ def measure_rows(reps: int):
     return out
 
 
+def measure_serving(count: int, rhos=(0.25, 0.5, 0.8, 0.95)):
+    """The serving loop on a seeded request stream: C=3, H and W uniform in
+    64..2048, p and q uniform in 1..8, method uniform, FP32 or BF16 by seed,
+    inputs generated on the device from each request's seed, outputs freed on
+    completion, 64 GB arena, 256 slots. Capacity is the throughput when every
+    request arrives at once; then Poisson arrivals at rho x capacity, served
+    with continuous batching and with one launch per request."""
+    import paper_2203_10670_amd as fc
+    import synth
+    meta = synth.request_stream(9, count, rate_per_s=0.0)
+    reqs = [fc.fcfs_request(r.p, r.q, r.method, r.pad, r.dtype, 1, r.c, r.h, r.w, None, r.seed, None) for r in meta]
+    srv = fc.Server(0, 64 << 30, 256)
+    fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_DISCARD_OUTPUTS, 1)
+
+    def run(arrivals, max_batch, subset=None):
+        rq = reqs if subset is None else reqs[:subset]
+        fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_MAX_BATCH, max_batch)
+        fc.fcfs_server_reset_stats(srv.handle)
+        st, tickets = fc.fcfs_server_replay(srv.handle, rq, arrivals[:len(rq)])
+        if st != 0:
+            raise fc.FcfsError(st, "fcfs_server_replay")
+        bad = 0
+        for t in tickets:
+            r = srv.wait(t)
+            bad += r.status != 0
+            srv.release(t)
+        p50, p99, rps, gbps = srv.stats()
+        return {"p50_us": round(p50, 1), "p99_us": round(p99, 1), "req_per_s": round(rps, 1),
+                "GBps": round(gbps, 1), "failed": int(bad)}
+
+    run([0.0] * 200, 0, subset=200)   # warm up
+    cap = run([0.0] * count, 0)
+    cap1 = run([0.0] * count, 1)
+    loads = []
+    rng = np.random.default_rng(10)
+    for rho in rhos:
+        rate = rho * cap["req_per_s"]
+        gaps = rng.exponential(1e6 / rate, size=count)
+        arr = list(np.cumsum(gaps) - gaps[0])
+        loads.append({"rho": rho, "offered_req_per_s": round(rate, 1),
+                      "batched": run(arr, 0), "one_launch_per_request": run(arr, 1)})
+    srv.close()
+    return {"requests": count, "capacity_batched": cap, "capacity_one_launch_per_request": cap1,
+            "loads": loads}
+
+
 def cpu_baseline(cases, x_np, target_planes: int):
     import oracle
     threads = oracle.threads()
@@ -249,6 +295,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=0)
     ap.add_argument("--no-rows", action="store_true", help="skip the other workloads (mix4, learned layer, ...)")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="requests of the serving run (0: skip)")
     ap.add_argument("--filter", default="", help="only cases whose name contains this text")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -388,6 +435,8 @@ def main():
         del f32, pc, x32, xbf
         torch.cuda.empty_cache()
         rows = measure_rows(max(3, args.steps))
+        if args.serve_requests > 0:
+            rows["serving"] = measure_serving(args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline and not args.filter:

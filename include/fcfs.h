@@ -241,6 +241,24 @@ fcfs_status fcfs_server_stats(fcfs_server_t server, double* p50_us, double* p99_
  * `value` batches fail as if their launch had failed (nothing is launched). */
 fcfs_status fcfs_server_debug(fcfs_server_t server, int hook, int64_t value);
 
+/* Server options. FCFS_SERVER_MAX_BATCH: most requests per batched launch
+ * (0 = no limit; 1 = one launch per request, for comparisons).
+ * FCFS_SERVER_DISCARD_OUTPUTS: 1 = free server-owned outputs as soon as a
+ * request finishes (its result then has y = NULL; for load tests). */
+typedef enum { FCFS_SERVER_MAX_BATCH = 1, FCFS_SERVER_DISCARD_OUTPUTS = 2 } fcfs_server_option;
+fcfs_status fcfs_server_config(fcfs_server_t server, int option, int64_t value);
+
+/* Submit `count` requests from the calling thread, request i when
+ * arrival_us[i] microseconds (non-decreasing) have passed since the call,
+ * waiting between submissions; tickets[i] receives each ticket. Returns the
+ * first submission error (earlier requests stay queued). For replaying
+ * arrival traces at rates a client thread in Python cannot keep. */
+fcfs_status fcfs_server_replay(fcfs_server_t server, const fcfs_request* reqs, const double* arrival_us,
+                               int64_t count, uint64_t* tickets);
+
+/* Forget the statistics gathered so far (latencies, counts, span). */
+fcfs_status fcfs_server_reset_stats(fcfs_server_t server);
+
 /* Finish every admitted request, stop the threads and free everything. Tickets
  * still pending are completed with FCFS_E_CANCELLED. */
 fcfs_status fcfs_server_destroy(fcfs_server_t server);

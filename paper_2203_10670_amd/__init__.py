@@ -24,6 +24,7 @@ __all__ = [
     "fcfs_version", "Plan", "resize", "FCFSFunction",
     "fcfs_request", "fcfs_result", "fcfs_server_create", "fcfs_submit", "fcfs_poll", "fcfs_wait",
     "fcfs_release", "fcfs_server_stats", "fcfs_server_debug", "fcfs_server_destroy", "Server",
+    "fcfs_server_config", "fcfs_server_replay", "fcfs_server_reset_stats",
     "device_view",
 ]
 
@@ -36,6 +37,7 @@ GRIDS = {"half": 0, "paper": 1, "asym": 2}
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 OK, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_AGAIN, E_PENDING, E_CANCELLED = range(8)
+FCFS_SERVER_MAX_BATCH, FCFS_SERVER_DISCARD_OUTPUTS = 1, 2
 
 
 class FcfsError(RuntimeError):
@@ -98,6 +100,10 @@ _sig("fcfs_release", [_P, ctypes.c_uint64])
 _sig("fcfs_server_stats", [_P, _D, _D, _D, _D])
 _sig("fcfs_server_debug", [_P, _I, _I64])
 _sig("fcfs_server_destroy", [_P])
+_sig("fcfs_server_config", [_P, _I, _I64])
+_sig("fcfs_server_replay", [_P, ctypes.POINTER(fcfs_request), ctypes.POINTER(ctypes.c_double), _I64,
+                            ctypes.POINTER(ctypes.c_uint64)])
+_sig("fcfs_server_reset_stats", [_P])
 _sig("fcfs_status_string", [_I], ctypes.c_char_p)
 _sig("fcfs_version", [], _I)
 
@@ -217,6 +223,25 @@ def fcfs_server_stats(server: int):
 
 def fcfs_server_debug(server: int, hook: int, value: int) -> int:
     return lib.fcfs_server_debug(server, hook, value)
+
+
+def fcfs_server_config(server: int, option: int, value: int) -> int:
+    return lib.fcfs_server_config(server, option, value)
+
+
+def fcfs_server_replay(server: int, reqs, arrival_us):
+    """Submit requests at arrival offsets (µs) from a native loop; returns
+    (status, tickets)."""
+    n = len(reqs)
+    arr = (fcfs_request * n)(*reqs)
+    t = (ctypes.c_double * n)(*arrival_us)
+    out = (ctypes.c_uint64 * n)()
+    st = lib.fcfs_server_replay(server, arr, t, n, out)
+    return st, list(out)
+
+
+def fcfs_server_reset_stats(server: int) -> int:
+    return lib.fcfs_server_reset_stats(server)
 
 
 def fcfs_server_destroy(server: int) -> None:

@@ -148,6 +148,8 @@ struct fcfs_server_ {
   int fail_allocs = 0;
   int fail_batches = 0;
   uint64_t frees = 0;                  // completions and releases: arena space may have come back
+  int max_batch = 0;                   // requests per launch (0: no limit)
+  bool discard_outputs = false;
 
   // statistics of finished requests
   std::vector<double> latencies;
@@ -203,7 +205,7 @@ void finish(fcfs_server_* s, Ticket& t, fcfs_status st, double when) {
     t.x_off = SIZE_MAX;
     t.x = nullptr;
   }
-  if (st != FCFS_OK && t.y_off != SIZE_MAX) {
+  if ((st != FCFS_OK || s->discard_outputs) && t.y_off != SIZE_MAX) {
     s->arena.release(t.y_off, t.y_bytes);
     t.y_off = SIZE_MAX;
     t.y = nullptr;
@@ -264,7 +266,8 @@ void scheduler_loop(fcfs_server_* s) {
     int ngen = 0;
     int64_t waves = 0, gblocks = 0;
     const double now = s->now_us();
-    while (!s->fifo.empty() && s->slots_used < s->max_slots) {
+    while (!s->fifo.empty() && s->slots_used < s->max_slots &&
+           (s->max_batch == 0 || (int)batch.tickets.size() < s->max_batch)) {
       const uint64_t id = s->fifo.front();
       Ticket& t = s->tickets[id];
       const size_t need = (t.req.x ? 0 : round_up(t.x_bytes)) + (t.req.y ? 0 : round_up(t.y_bytes));
@@ -567,6 +570,47 @@ fcfs_status fcfs_server_debug(fcfs_server_t s, int hook, int64_t value) {
   if (hook == 1) s->fail_allocs = (int)value;
   else if (hook == 2) s->fail_batches = (int)value;
   else return FCFS_E_INVAL;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_server_config(fcfs_server_t s, int option, int64_t value) {
+  if (!s || value < 0) return FCFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (option == FCFS_SERVER_MAX_BATCH) s->max_batch = (int)std::min<int64_t>(value, 1 << 30);
+  else if (option == FCFS_SERVER_DISCARD_OUTPUTS) s->discard_outputs = value != 0;
+  else return FCFS_E_INVAL;
+  s->cv_sched.notify_all();
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_server_replay(fcfs_server_t s, const fcfs_request* reqs, const double* arrival_us, int64_t count,
+                               uint64_t* tickets) {
+  if (!s || count < 0 || (count > 0 && (!reqs || !arrival_us || !tickets))) return FCFS_E_INVAL;
+  const auto start = std::chrono::steady_clock::now();
+  for (int64_t i = 0; i < count; ++i) {
+    const auto due = start + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                 std::chrono::duration<double, std::micro>(arrival_us[i]));
+    // sleep while far from the due time, then spin for precision
+    for (;;) {
+      const auto now = std::chrono::steady_clock::now();
+      if (now >= due) break;
+      if (due - now > std::chrono::microseconds(200)) std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+    }
+    fcfs_status st;
+    while ((st = fcfs_submit(s, &reqs[i], &tickets[i])) == FCFS_E_AGAIN) std::this_thread::yield();
+    if (st != FCFS_OK) return st;
+  }
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_server_reset_stats(fcfs_server_t s) {
+  if (!s) return FCFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->latencies.clear();
+  s->first_arrive = -1;
+  s->last_done = 0;
+  s->done_bytes = 0;
+  s->done_count = 0;
   return FCFS_OK;
 }
 

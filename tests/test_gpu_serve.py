@@ -123,3 +123,26 @@ def test_destroy_with_pending_requests():
     for s in range(40):
         srv.submit(2, 1, "nearest", "zero", "f32", (1, 3, 300, 300), seed=s)
     srv.close()   # finishes admitted work, cancels the rest, frees everything
+
+
+def test_replay_one_launch_per_request_and_discard():
+    import paper_2203_10670_amd as fc
+    srv = fc.Server(0, 2 << 30, 32)
+    meta = synth.request_stream(21, 60, rate_per_s=0.0, hw_lo=16, hw_hi=300)
+    reqs = [fc.fcfs_request(r.p, r.q, r.method, r.pad, r.dtype, 1, r.c, r.h, r.w, None, r.seed, None)
+            for r in meta]
+    arr = [20.0 * i for i in range(len(reqs))]
+    for max_batch in (1, 0):
+        assert fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_MAX_BATCH, max_batch) == 0
+        assert fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_DISCARD_OUTPUTS, 1) == 0
+        assert fc.fcfs_server_reset_stats(srv.handle) == 0
+        st, tickets = fc.fcfs_server_replay(srv.handle, reqs, arr)
+        assert st == 0
+        for t in tickets:
+            r = srv.wait(t)
+            assert r.status == 0 and r.y is None
+            srv.release(t)
+        p50, p99, rps, gbps = srv.stats()
+        assert 0 < p50 <= p99 and rps > 0
+    assert fc.fcfs_server_config(srv.handle, 99, 1) == fc.E_INVAL
+    srv.close()
