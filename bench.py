@@ -65,7 +65,7 @@ def case_bytes(fc, plan, shape, esize: int) -> int:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fwd.hip", "api.cpp", "fcfs_internal.h"):
+    for f in ("fwd_kernel.h", "fwd_f32.hip", "api.cpp", "fcfs_internal.h"):
         with open(os.path.join(ROOT, "paper_2203_10670_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -286,6 +286,60 @@ def summarize(d):
             print("%-60s %-12s %8d %16.1f" % (short, c, n, v / n))
 
 
+def _counter_rows(d, counter):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+    return rows
+
+
+def _kernel_id(name):
+    """Instance id of a forward kernel name fcfs_fwd_kernel<DT, T, KC, L, LEARNED>."""
+    import re
+    m = re.search(r"fcfs_fwd_kernel<(\d+), (\d+), (\d+), (\d+), (true|false)>", name)
+    if not m:
+        return None
+    dt, t, kc, sl = (int(m.group(i)) for i in range(1, 5))
+    return dt * 1000 + t * 100 + kc * 10 + sl + (10000 if m.group(5) == "true" else 0)
+
+
+def write_traffic(fetch_dir, write_dir):
+    """HBM bytes per launch of each forward kernel instance from two counter
+    runs: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what
+    the same counter reads for a 1 GiB device copy (1 GiB read, 1 GiB
+    written) in the same run."""
+    out = {"source_hash": source_hash(), "kernels": {}}
+    scale = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not copies:
+            raise SystemExit("no copy calibration dispatch in %s" % d)
+        scale[counter] = (1 << 20) / (sum(copies) / len(copies))   # KiB of a 1 GiB copy / measured
+        per = {}
+        for r in rows:
+            kid = _kernel_id(r["Kernel_Name"])
+            if kid is None:
+                continue
+            per.setdefault(kid, []).append(float(r["Counter_Value"]))
+        for kid, v in per.items():
+            e = out["kernels"].setdefault(str(kid), {})
+            e[counter + "_KiB_raw"] = sum(v) / len(v)
+            e[counter + "_bytes"] = sum(v) / len(v) * 1024 * scale[counter]
+            e["dispatches_" + counter] = len(v)
+    for e in out["kernels"].values():
+        if "FETCH_SIZE_bytes" in e and "WRITE_SIZE_bytes" in e:
+            e["bytes_per_launch"] = int(e["FETCH_SIZE_bytes"] + e["WRITE_SIZE_bytes"])
+    out["scale"] = scale
+    path = os.path.join(ROOT, "profiles", "fwd_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,9 +354,15 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--summarize", metavar="DIR", help="summarise rocprofv3 CSV output under DIR and exit")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn FETCH_SIZE / WRITE_SIZE counter runs (with --copy-calibration) into "
+                         "profiles/fwd_traffic.json and exit")
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize)
+        return
+    if args.traffic:
+        write_traffic(*args.traffic)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the rescale path has no multi-GPU mode "
