@@ -141,8 +141,11 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
  * tests and benchmarks; enqueues nothing). kernel_id identifies the compiled
  * kernel instance: dtype*1000 + taps*100 + column groups per lane*10 + staged
  * row dwords per lane (+ 10000 for the learned depthwise layer, 20000 for the
- * channel-mixing layer). Any
- * output pointer may be NULL. Errors: as fcfs_forward's argument checks. */
+ * channel-mixing layer, 50000 for the paired 16-bit instance, where the last
+ * digit counts staged sample pairs; fcfs_forward takes that instance when
+ * both widths are even and x and y are 4-byte aligned, which this call
+ * assumes). Any output pointer may be NULL. Errors: as fcfs_forward's
+ * argument checks. */
 fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
                                 int64_t h, int64_t w, int* kernel_id, int* strip_width,
                                 int* band_cells, int64_t* waves);

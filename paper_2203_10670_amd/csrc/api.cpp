@@ -126,22 +126,22 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
 }
 
 static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                                bool batch, FwdGeom* g);
+                                bool batch, bool pair_ok, FwdGeom* g);
 
 fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                              FwdGeom* g) {
-  return forward_geom(plan, planes, h, w, ho, wo, false, g);
+                              bool pair_ok, FwdGeom* g) {
+  return forward_geom(plan, planes, h, w, ho, wo, false, pair_ok, g);
 }
 
 // The batched kernel carries the instances with 4 or 1 column groups per lane
 // and 8 staged slots.
 fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
                                     FwdGeom* g) {
-  return forward_geom(plan, planes, h, w, ho, wo, true, g);
+  return forward_geom(plan, planes, h, w, ho, wo, true, false, g);
 }
 
 static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                                bool batch, FwdGeom* g) {
+                                bool batch, bool pair_ok, FwdGeom* g) {
   (void)h;
   (void)w;
   const AxisTable& aw = plan->aw;
@@ -160,6 +160,11 @@ static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, i
   if (seg(tw) > 512) return FCFS_E_UNSUPPORTED;
   const int need = seg(tw);
   g->slots = batch ? 8 : (need <= 128 ? 2 : (need <= 256 ? 4 : 8));
+  // Paired 16-bit I/O: whole strips of 64*kc columns (kc even), and the staged
+  // segment, which may start one column early to stay pair-aligned, fits in
+  // 128 or 256 pairs.
+  g->paired = pair_ok && !batch && !learned && kc % 2 == 0 && tw == 64 * kc && need + 1 <= 512;
+  if (g->paired) g->slots = need + 1 <= 256 ? 2 : 4;
   g->kc = kc;
   g->tw = tw;
   g->strips = (wo + tw - 1) / tw;
@@ -423,8 +428,11 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
   a.pad = plan->pad;
   a.th = plan->ah;
   a.tw_tab = plan->aw;
+  // 16-bit samples can move two per dword when every row starts 4-byte aligned
+  const bool pair_ok = dtype != FCFS_F32 && w % 2 == 0 && wo % 2 == 0 &&
+                       (reinterpret_cast<uintptr_t>(x) & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 3) == 0;
   FwdGeom g;
-  st = plan_forward_geom(plan, a.planes, a.H, a.W, a.Ho, a.Wo, &g);
+  st = plan_forward_geom(plan, a.planes, a.H, a.W, a.Ho, a.Wo, pair_ok, &g);
   if (st != FCFS_OK) return st;
   a.tw = g.tw;
   a.strips = g.strips;
@@ -449,10 +457,12 @@ fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   FwdGeom g;
   std::memset(&g, 0, sizeof(g));
   if (n > 0 && c_in > 0 && h > 0 && w > 0) {
-    st = plan_forward_geom(plan, n * c_in, (int)h, (int)w, (int)ho, (int)wo, &g);
+    const bool pair_ok = dtype != FCFS_F32 && w % 2 == 0 && wo % 2 == 0;   // tensors taken 4-byte aligned
+    st = plan_forward_geom(plan, n * c_in, (int)h, (int)w, (int)ho, (int)wo, pair_ok, &g);
     if (st != FCFS_OK) return st;
   }
   int id = (int)dtype * 1000 + plan->ah.T * 100 + g.kc * 10 + g.slots;
+  if (g.paired) id += 50000;
   if (plan->method == FCFS_LEARNED_DW4) id += 10000;
   if (plan->method == FCFS_LEARNED_MIX4) id += 20000;
   if (kernel_id) *kernel_id = id;

@@ -44,6 +44,7 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
 struct FwdGeom {
   int kc;            // output-column groups per lane (1, 2 or 4)
   int slots;         // staged row-segment dwords per lane (2, 4 or 8)
+  bool paired;       // 16-bit samples move in pairs (slots then count pairs)
   int tw;            // output columns per wave strip
   int strips;        // strips per plane
   int band_cells;    // hidden-layer cells (groups of p output rows) per band
@@ -148,6 +149,6 @@ fcfs_status launch_forward_f16(int method, const FwdArgs& a, const FwdGeom& g, h
 
 // Host-side launch geometry for a plane of (h, w) -> (ho, wo).
 fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho,
-                              int wo, FwdGeom* g);
+                              int wo, bool pair_ok, FwdGeom* g);
 
 }  // namespace fcfs

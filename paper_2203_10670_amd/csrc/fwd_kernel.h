@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fcfs_internal.h"
 
 namespace fcfs {
@@ -62,6 +64,12 @@ template <> struct Store<FCFS_F32> {
 };
 template <> struct Store<FCFS_BF16> {
   using T = uint16_t;
+  static __device__ __forceinline__ float from_bits(uint32_t b) { return __uint_as_float(b << 16); }
+  static __device__ __forceinline__ uint32_t to_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // quiet NaN
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;                     // round to nearest even
+  }
   static __device__ __forceinline__ float load(const T* p) {
     const uint32_t b = *p;
     return __uint_as_float(b << 16);
@@ -77,6 +85,10 @@ template <> struct Store<FCFS_BF16> {
 };
 template <> struct Store<FCFS_F16> {
   using T = _Float16;
+  static __device__ __forceinline__ float from_bits(uint32_t b) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+  }
+  static __device__ __forceinline__ uint32_t to_bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
   static __device__ __forceinline__ float load(const T* p) { return (float)*p; }
   static __device__ __forceinline__ void store(T* p, float v) {
     if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store((_Float16)v, p);
@@ -113,10 +125,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // The per-wave work of the forward: wave `wid` of the launch described by `a`
 // (a may live in the kernel-argument segment or in device memory).
-template <int DT, int T, int KC, int L, bool LEARNED>
+// PAIR (16-bit storage, even widths, 4-byte aligned tensors): every lane
+// loads and stores two adjacent samples as one dword; its output columns are
+// adjacent pairs ow0 + 2*lane + 128*g + {0, 1}.
+template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false>
 __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslot, int lane, float* smem) {
   using S = Store<DT>;
   using TS = typename S::T;
+  static_assert(!PAIR || (DT != FCFS_F32 && KC % 2 == 0 && L <= 4), "paired I/O: 16-bit, column pairs");
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
 
@@ -131,7 +147,8 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   const int m1 = min(m0 + a.band_cells, a.Mh);
 
   const int n0 = ow0 / TW.p;
-  const int cs = TW.q * n0 + TW.omin;   // first input column staged
+  // first input column staged (even in paired mode, so pairs are aligned)
+  const int cs = PAIR ? ((TW.q * n0 + TW.omin) & ~1) : TW.q * n0 + TW.omin;
 
   float* row = smem + wslot * kRowMax;
   float* wl = nullptr;
@@ -143,7 +160,8 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
     wave_lds_sync();
   }
 
-  // Output columns of this lane: ow0 + lane + 64*c.
+  // Output columns of this lane: ow0 + lane + 64*c (paired: ow0 + 2*lane +
+  // 128*(c/2) + c%2).
   int pos[KC];
   int ocol[KC];
   int wbase[KC];
@@ -151,7 +169,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   float wc[KC][T];
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
-    const int ow = ow0 + lane + 64 * c;
+    const int ow = PAIR ? ow0 + 2 * lane + 128 * (c >> 1) + (c & 1) : ow0 + lane + 64 * c;
     cvalid[c] = ow < owEnd;
     const int owc = cvalid[c] ? ow : ow0;
     const int n = owc / TW.p;
@@ -164,15 +182,28 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   }
 
   // Source column of each staged slot lane + 64*s, clamped into the row;
-  // ckeep = false where zero padding supplies the value.
-  int scol[L];
-  bool ckeep[L];
+  // ckeep = false where zero padding supplies the value. Paired: slot s holds
+  // columns cs + 2*(lane + 64*s) + {0, 1}; pairs wholly inside the row load as
+  // one dword, the others (edge strips only) fetch each sample on its own.
+  constexpr int E = PAIR ? 2 : 1;
+  int scol[L][E];
+  bool ckeep[L][E];
+  int pcol[L];
+  bool pin[L];
 #pragma unroll
   for (int s = 0; s < L; ++s) {
-    const int src = pad_source(cs + lane + 64 * s, a.W, a.pad);
-    ckeep[s] = src >= 0;
-    scol[s] = src >= 0 ? src : 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int src = pad_source(cs + E * (lane + 64 * s) + e, a.W, a.pad);
+      ckeep[s][e] = src >= 0;
+      scol[s][e] = src >= 0 ? src : 0;
+    }
+    const int c0 = cs + 2 * (lane + 64 * s);
+    pin[s] = PAIR && c0 >= 0 && c0 + 1 < a.W;
+    pcol[s] = pin[s] ? c0 : 0;
   }
+  bool edge = false;
+  if constexpr (PAIR) edge = cs < 0 || cs + 128 * L > a.W;   // some pair leaves the row
 
   const TS* xplane = reinterpret_cast<const TS*>(a.x) + plane * (int64_t)a.H * a.W;
   TS* yplane = reinterpret_cast<TS*>(a.y) + plane * (int64_t)a.Ho * a.Wo;
@@ -189,14 +220,30 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
     return pad_source(r, a.H, a.pad);
   };
 
-  float buf[kPrefetch][L];
+  // prefetched rows: FP32 values, or raw sample pairs in paired mode
+  using Raw = typename std::conditional<PAIR, uint32_t, float>::type;
+  Raw buf[kPrefetch][L];
+  uint32_t fix[kPrefetch][PAIR ? L : 1];   // edge pairs assembled sample by sample
   int bsrc[kPrefetch];
-  auto load_row = [&](int r, float (&dst)[L], int& src_out) {
+  auto load_row = [&](int r, Raw (&dst)[L], uint32_t (&fx)[PAIR ? L : 1], int& src_out) {
     const int sr = fetch_row(r);
     src_out = sr;
     const TS* src = xplane + (int64_t)(sr < 0 ? 0 : sr) * a.W;
+    if constexpr (PAIR) {
 #pragma unroll
-    for (int s = 0; s < L; ++s) dst[s] = S::load(src + scol[s]);
+      for (int s = 0; s < L; ++s) dst[s] = *reinterpret_cast<const uint32_t*>(src + pcol[s]);
+      if (edge) {
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+          const uint32_t lo = *reinterpret_cast<const uint16_t*>(src + scol[s][0]);
+          const uint32_t hi = *reinterpret_cast<const uint16_t*>(src + scol[s][1]);
+          fx[s] = lo | (hi << 16);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < L; ++s) dst[s] = S::load(src + scol[s][0]);
+    }
   };
 
   // FIFO of the last T rows: fixed methods keep the width-filtered value per
@@ -211,7 +258,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
       for (int b = 0; b < FT; ++b) fifo[c][t][b] = 0.f;
 
 #pragma unroll
-  for (int d = 0; d < kPrefetch; ++d) load_row(rs + d, buf[d], bsrc[d]);
+  for (int d = 0; d < kPrefetch; ++d) load_row(rs + d, buf[d], fix[d], bsrc[d]);
 
   int rho = mod_pos(rs, TH.q);
   for (int rb = rs; rb <= re; rb += kPrefetch) {
@@ -221,9 +268,18 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
       if (r > re) break;
       // stage the row (zero padding applied here), then refill the slot
       const bool zrow = bsrc[d] < 0;
+      if constexpr (PAIR) {
 #pragma unroll
-      for (int s = 0; s < L; ++s) row[lane + 64 * s] = (ckeep[s] && !zrow) ? buf[d][s] : 0.f;
-      load_row(r + kPrefetch, buf[d], bsrc[d]);
+        for (int s = 0; s < L; ++s) {
+          const uint32_t raw = (edge && !pin[s]) ? fix[d][s] : buf[d][s];
+          row[2 * (lane + 64 * s)] = (ckeep[s][0] && !zrow) ? S::from_bits(raw & 0xffffu) : 0.f;
+          row[2 * (lane + 64 * s) + 1] = (ckeep[s][1] && !zrow) ? S::from_bits(raw >> 16) : 0.f;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < L; ++s) row[lane + 64 * s] = (ckeep[s][0] && !zrow) ? buf[d][s] : 0.f;
+      }
+      load_row(r + kPrefetch, buf[d], fix[d], bsrc[d]);
       wave_lds_sync();
       float cur[KC][FT];
 #pragma unroll
@@ -258,6 +314,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
         const int m = (r - (TH.off[j] + T - 1)) / TH.q;   // exact: r = last tap (mod q)
         if (m < m0 || m >= m1) continue;
         TS* orow = yplane + (int64_t)(TH.p * m + j) * a.Wo;
+        float outv[KC];
         if constexpr (LEARNED) {
           const float* wj = wl + j * TW.p * 16;
 #pragma unroll
@@ -268,12 +325,11 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
             for (int t = 0; t < T; ++t)
 #pragma unroll
               for (int b = 0; b < T; ++b) acc = __builtin_fmaf(wk[t * 4 + b], fifo[c][t][b], acc);
-            if (cvalid[c]) S::store(orow + ocol[c], acc);
+            outv[c] = acc;
           }
         } else if constexpr (T == 1) {
 #pragma unroll
-          for (int c = 0; c < KC; ++c)
-            if (cvalid[c]) S::store(orow + ocol[c], fifo[c][0][0]);
+          for (int c = 0; c < KC; ++c) outv[c] = fifo[c][0][0];
         } else {
           float wv[T];
 #pragma unroll
@@ -283,8 +339,20 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
             float acc = wv[0] * fifo[c][0][0];
 #pragma unroll
             for (int t = 1; t < T; ++t) acc = __builtin_fmaf(wv[t], fifo[c][t][0], acc);
-            if (cvalid[c]) S::store(orow + ocol[c], acc);
+            outv[c] = acc;
           }
+        }
+        if constexpr (PAIR) {
+          // both columns of a pair are valid or neither (even widths and starts)
+#pragma unroll
+          for (int g = 0; g < KC / 2; ++g)
+            if (cvalid[2 * g])
+              __builtin_nontemporal_store(S::to_bits(outv[2 * g]) | (S::to_bits(outv[2 * g + 1]) << 16),
+                                          reinterpret_cast<uint32_t*>(orow + ocol[2 * g]));
+        } else {
+#pragma unroll
+          for (int c = 0; c < KC; ++c)
+            if (cvalid[c]) S::store(orow + ocol[c], outv[c]);
         }
       }
       rho = (rho + 1 == TH.q) ? 0 : rho + 1;
@@ -292,7 +360,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   }
 }
 
-template <int DT, int T, int KC, int L, bool LEARNED>
+template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false>
 __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63;
@@ -309,7 +377,7 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   }
   const int64_t wid = blk * kWaves + wslot;
   if (wid >= a.waves) return;
-  fwd_wave<DT, T, KC, L, LEARNED>(a, wid, wslot, lane, smem);
+  fwd_wave<DT, T, KC, L, LEARNED, PAIR>(a, wid, wslot, lane, smem);
 }
 
 template <int DT, int T, int KC, bool LEARNED>
@@ -318,6 +386,13 @@ fcfs_status launch_l(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
   const dim3 grid((unsigned)((g.waves + kWaves - 1) / kWaves));
   size_t lds = sizeof(float) * kWaves * kRowMax;
   if (LEARNED) lds += sizeof(float) * kWaves * a.th.p * a.tw_tab.p * 16;
+  if constexpr (DT != FCFS_F32 && !LEARNED && KC % 2 == 0) {
+    if (g.paired) {
+      if (g.slots <= 2) hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED, true>), grid, block, lds, stream, a);
+      else hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED, true>), grid, block, lds, stream, a);
+      return hipGetLastError() == hipSuccess ? FCFS_OK : FCFS_E_DEVICE;
+    }
+  }
   switch (g.slots) {
     case 2: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED>), grid, block, lds, stream, a); break;
     case 4: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED>), grid, block, lds, stream, a); break;

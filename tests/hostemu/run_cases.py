@@ -81,6 +81,7 @@ def main():
     lib.fcfs_forward.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 4 + [P, P, ctypes.c_int64, P, P]
     lib.fcfs_output_size.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.fcfs_forward_config.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 4 + [P, P, P, P]
     lib.fcfs_backward_workspace.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 5 + [ctypes.POINTER(ctypes.c_size_t)]
     lib.fcfs_backward.argtypes = [P, ctypes.c_int] + [ctypes.c_int64] * 4 + [P, P, ctypes.c_int64, P, P, P, P,
                                                                              ctypes.c_size_t, P]
@@ -114,7 +115,17 @@ def main():
             if not ok:
                 sys.exit(1)
             continue
-        y = np.zeros((N, Co, ho.value, wo.value), dtype=xs.dtype)
+        if c.get("expect_paired") is not None:
+            kid = ctypes.c_int()
+            assert lib.fcfs_forward_config(plan, DT[dt], N, C, H, W, ctypes.byref(kid), None, None, None) == 0
+            # (the configuration query takes tensors to be aligned)
+            assert (kid.value >= 50000) == c["expect_paired"], kid.value
+        if c.get("misalign"):
+            # output one element past a 4-byte boundary: the unpaired instance
+            ybuf = np.zeros(N * Co * ho.value * wo.value + 1, dtype=xs.dtype)
+            y = ybuf[1:].reshape(N, Co, ho.value, wo.value)
+        else:
+            y = np.zeros((N, Co, ho.value, wo.value), dtype=xs.dtype)
         st = lib.fcfs_forward(plan, DT[dt], N, C, H, W, xs.ctypes.data, wptr, Co, y.ctypes.data, None)
         if c.get("expect_status") is not None:
             ok = st == c["expect_status"]

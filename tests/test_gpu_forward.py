@@ -57,6 +57,56 @@ def test_tiled_16bit(dtype, p, q, method):
     assert_parity(y, x, p, q, method, "reflect", dtype, what=f"{dtype} {p}/{q} {method}")
 
 
+PAIRED = [(3, 2, 300), (2, 3, 700), (5, 4, 208), (4, 5, 400), (3, 4, 256), (27, 11, 440), (1, 1, 258),
+          (7, 3, 1026)]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("p,q,W", PAIRED)
+@pytest.mark.parametrize("method", METHODS)
+def test_paired_16bit(dtype, p, q, W, method):
+    # even widths: the instance that moves two 16-bit samples per dword, with
+    # edge strips on both sides, several strips and bands, all pads
+    import paper_2203_10670_amd as fc
+    pad = PADS[(p + q + W) % 3]
+    pl = fc.Plan(p, q, method, pad)
+    kid = fc.fcfs_forward_config(pl.handle, {"bf16": 1, "f16": 2}[dtype], 2, 3, 45, W)[0]
+    assert kid >= 50000, kid
+    x = storage_round(synth.normal(400 + p + q, (2, 3, 45, W)), dtype)
+    _say("paired", dtype, p, q, W, method, pad)
+    y = gpu_forward(x, p, q, method, pad, dtype)
+    assert_parity(y, x, p, q, method, pad, dtype, what=f"paired {dtype} {p}/{q} {W} {method} {pad}")
+
+
+def test_paired_guard_bands_and_misaligned():
+    # a 16-bit output in the middle of a larger buffer, 4-byte aligned (paired)
+    # and 2-byte aligned (unpaired): nothing outside may change
+    import torch
+    import paper_2203_10670_amd as fc
+    for dtype in ("bf16", "f16"):
+        td = {"bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+        xs = storage_round(synth.normal(11, (2, 3, 51, 300)), dtype)
+        x = torch.from_numpy(xs).cuda().to(td)
+        for G in (4096, 4097):
+            for p, q, m in [(3, 2, "bicubic"), (2, 3, "bilinear"), (4, 5, "nearest")]:
+                pl = fc.Plan(p, q, m, "reflect")
+                ho, wo = pl.output_size(51, 300)
+                nout = 2 * 3 * ho * wo
+                buf = torch.full((nout + 2 * G,), 1234.0, device="cuda", dtype=td)
+                y = buf[G:G + nout].view(2, 3, ho, wo)
+                pl.forward(x, out=y)
+                torch.cuda.synchronize()
+                assert bool((buf[:G] == 1234.0).all()) and bool((buf[G + nout:] == 1234.0).all())
+                assert_parity(y.float().cpu().numpy(), xs, p, q, m, "reflect", dtype, what=f"{dtype} G={G}")
+        # misaligned input as well
+        xb = torch.empty((2 * 3 * 51 * 300 + 1,), device="cuda", dtype=td)
+        xv = xb[1:].view(2, 3, 51, 300)
+        xv.copy_(x)
+        y = fc.Plan(3, 2, "bicubic", "zero").forward(xv)
+        torch.cuda.synchronize()
+        assert_parity(y.float().cpu().numpy(), xs, 3, 2, "bicubic", "zero", dtype, what="misaligned x")
+
+
 def test_exhaustive_small():
     # every p, q in 1..8, each method and pad, on small ragged shapes
     sizes = [(1, 1), (2, 3), (3, 2), (5, 7), (7, 4)]

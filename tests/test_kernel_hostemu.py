@@ -56,6 +56,23 @@ def test_storage_types():
     _run(cases)
 
 
+def test_paired_16bit_io():
+    # even widths and aligned tensors take the paired instance: left and right
+    # edge strips, several strips, staged segments of 128 and 256 pairs; the
+    # misaligned output takes the unpaired one (the sanitizers flag a
+    # misaligned dword store)
+    cases = []
+    for i, (p, q, m, W) in enumerate([(3, 2, "bicubic", 300), (2, 3, "bilinear", 700), (4, 5, "bicubic", 400),
+                                      (5, 4, "bilinear", 208), (3, 4, "bicubic", 256), (27, 11, "nearest", 440),
+                                      (1, 1, "bicubic", 258), (3, 2, "nearest", 132)]):
+        for dt in ["bf16", "f16"]:
+            cases.append({"p": p, "q": q, "method": m, "pad": ["zero", "replicate", "reflect"][i % 3],
+                          "dtype": dt, "shape": [1, 2, 11, W], "expect_paired": True})
+    cases.append({"p": 3, "q": 2, "method": "bicubic", "pad": "reflect", "dtype": "bf16", "shape": [1, 2, 9, 300],
+                  "misalign": True, "expect_paired": True})
+    _run(cases)
+
+
 def test_grids_anisotropic_degenerate():
     _run([{"p": 3, "q": 2, "pw": 4, "qw": 5, "method": "bicubic", "pad": "zero", "shape": [1, 1, 19, 80]},
           {"p": 3, "q": 2, "method": "bilinear", "pad": "reflect", "grid": "paper", "shape": [1, 1, 12, 40]},
