@@ -50,6 +50,16 @@ def _load():
     if not os.path.exists(library_path):
         raise ImportError("libfcfs.so is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
                           "or `python paper_2203_10670_amd/build.py` first (%s)" % library_path)
+    # The library must use the HIP runtime torch uses (streams and device
+    # state are per runtime). torch ships its own libamdhip64, which its
+    # libraries ask for by an unversioned name: loaded after the library
+    # (which asks for libamdhip64.so.7 and gets the system one), torch would
+    # bring a second runtime into the process. Loading torch first makes the
+    # library bind to torch's runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     return ctypes.CDLL(library_path)
 
 

@@ -125,23 +125,34 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
   return FCFS_OK;
 }
 
-static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                                bool batch, bool pair_ok, FwdGeom* g);
+void fill_emit(const AxisTable& t, EmitRec* out) {
+  std::memset(out, 0, sizeof(EmitRec) * kMaxFactor);
+  for (int e = 0; e < t.emit_start[t.q]; ++e) {
+    const int j = t.emit_list[e];
+    const int last = t.off[j] + t.T - 1;   // last tap row of cell 0, = e's residue (mod q)
+    out[e].j = j;
+    out[e].lag = (last - mod_pos(last, t.q)) / t.q;
+    for (int k = 0; k < 4; ++k) out[e].w[k] = t.w[j][k];
+  }
+}
 
-fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
+static fcfs_status forward_geom(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho,
+                                int wo, bool batch, bool pair_ok, FwdGeom* g);
+
+fcfs_status plan_forward_geom(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho, int wo,
                               bool pair_ok, FwdGeom* g) {
-  return forward_geom(plan, planes, h, w, ho, wo, false, pair_ok, g);
+  return forward_geom(plan, dtype, planes, h, w, ho, wo, false, pair_ok, g);
 }
 
 // The batched kernel carries the instances with 4 or 1 column groups per lane
 // and 8 staged slots.
-fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                                    FwdGeom* g) {
-  return forward_geom(plan, planes, h, w, ho, wo, true, false, g);
+fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho,
+                                    int wo, FwdGeom* g) {
+  return forward_geom(plan, dtype, planes, h, w, ho, wo, true, false, g);
 }
 
-static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                                bool batch, bool pair_ok, FwdGeom* g) {
+static fcfs_status forward_geom(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho,
+                                int wo, bool batch, bool pair_ok, FwdGeom* g) {
   (void)h;
   (void)w;
   const AxisTable& aw = plan->aw;
@@ -172,20 +183,34 @@ static fcfs_status forward_geom(const fcfs_plan_* plan, int64_t planes, int h, i
   // Bands of cells. Consecutive waves take the strips of one band, then the
   // next band of the same plane, so the waves in flight together work on
   // nearby rows of few planes. A band of c cells streams q*(c-1) + span input
-  // rows; bands are sized to about FCFS_FWD_BAND_ROWS rows: small enough for
-  // many waves (latency hiding, a short tail at the end of the launch), large
-  // enough that the span - q rows re-read above each band stay a modest share.
+  // rows; bands are sized to about a set number of rows per tap count: small
+  // enough for many waves (a short tail at the end of the launch), large
+  // enough that the span - q rows re-read above each band, and the per-wave
+  // set-up, stay a modest share. 16-bit storage moves half the bytes per row
+  // for the same instructions, so it takes longer bands.
 #ifndef FCFS_FWD_BAND_ROWS_T1
-#define FCFS_FWD_BAND_ROWS_T1 4
+#define FCFS_FWD_BAND_ROWS_T1 6
 #endif
 #ifndef FCFS_FWD_BAND_ROWS_T2
-#define FCFS_FWD_BAND_ROWS_T2 12
+#define FCFS_FWD_BAND_ROWS_T2 10
 #endif
 #ifndef FCFS_FWD_BAND_ROWS_T4
-#define FCFS_FWD_BAND_ROWS_T4 16
+#define FCFS_FWD_BAND_ROWS_T4 14
+#endif
+#ifndef FCFS_FWD_BAND_ROWS16_T1
+#define FCFS_FWD_BAND_ROWS16_T1 16
+#endif
+#ifndef FCFS_FWD_BAND_ROWS16_T2
+#define FCFS_FWD_BAND_ROWS16_T2 24
+#endif
+#ifndef FCFS_FWD_BAND_ROWS16_T4
+#define FCFS_FWD_BAND_ROWS16_T4 32
 #endif
   const int span_h = ah.omax - ah.omin + 1;
-  const int rows = ah.T == 1 ? FCFS_FWD_BAND_ROWS_T1 : (ah.T == 2 ? FCFS_FWD_BAND_ROWS_T2 : FCFS_FWD_BAND_ROWS_T4);
+  const int rows = dtype == FCFS_F32
+                       ? (ah.T == 1 ? FCFS_FWD_BAND_ROWS_T1 : (ah.T == 2 ? FCFS_FWD_BAND_ROWS_T2 : FCFS_FWD_BAND_ROWS_T4))
+                       : (ah.T == 1 ? FCFS_FWD_BAND_ROWS16_T1
+                                    : (ah.T == 2 ? FCFS_FWD_BAND_ROWS16_T2 : FCFS_FWD_BAND_ROWS16_T4));
   // ... and at least four output rows per wave
   const int cells = std::max({1, (rows - span_h) / ah.q + 1, (4 + ah.p - 1) / ah.p});
   g->band_cells = cells;
@@ -428,11 +453,12 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
   a.pad = plan->pad;
   a.th = plan->ah;
   a.tw_tab = plan->aw;
+  fill_emit(plan->ah, a.emit);
   // 16-bit samples can move two per dword when every row starts 4-byte aligned
   const bool pair_ok = dtype != FCFS_F32 && w % 2 == 0 && wo % 2 == 0 &&
                        (reinterpret_cast<uintptr_t>(x) & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 3) == 0;
   FwdGeom g;
-  st = plan_forward_geom(plan, a.planes, a.H, a.W, a.Ho, a.Wo, pair_ok, &g);
+  st = plan_forward_geom(plan, dtype, a.planes, a.H, a.W, a.Ho, a.Wo, pair_ok, &g);
   if (st != FCFS_OK) return st;
   a.tw = g.tw;
   a.strips = g.strips;
@@ -458,7 +484,7 @@ fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   std::memset(&g, 0, sizeof(g));
   if (n > 0 && c_in > 0 && h > 0 && w > 0) {
     const bool pair_ok = dtype != FCFS_F32 && w % 2 == 0 && wo % 2 == 0;   // tensors taken 4-byte aligned
-    st = plan_forward_geom(plan, n * c_in, (int)h, (int)w, (int)ho, (int)wo, pair_ok, &g);
+    st = plan_forward_geom(plan, dtype, n * c_in, (int)h, (int)w, (int)ho, (int)wo, pair_ok, &g);
     if (st != FCFS_OK) return st;
   }
   int id = (int)dtype * 1000 + plan->ah.T * 100 + g.kc * 10 + g.slots;

@@ -52,6 +52,17 @@ struct FwdGeom {
   int64_t waves;     // total waves
 };
 
+// Height emission record of the forward kernel: when input row r arrives
+// (r = q*rq + rho), the entries emit_start[rho] .. emit_start[rho+1] - 1
+// finish output row p*(rq - lag) + j, with the phase's height taps w.
+struct alignas(32) EmitRec {
+  int j;
+  int lag;
+  float w[4];
+  int pad_[2];
+};
+void fill_emit(const AxisTable& t, EmitRec* out);
+
 struct FwdArgs {
   const void* x;
   void* y;
@@ -63,6 +74,7 @@ struct FwdArgs {
   int tw, strips, band_cells, bands;
   int64_t waves;
   AxisTable th, tw_tab;
+  EmitRec emit[kMaxFactor];   // height emission records (from th)
 };
 
 struct BwdArgs {
@@ -131,8 +143,8 @@ constexpr int kGenPerBlock = 256 * 16;   // elements per generator block
 fcfs_status launch_forward_batch(const BatchArgs& b, hipStream_t stream);
 fcfs_status launch_generate(const GenArgs& g, hipStream_t stream);
 // Launch geometry for a batched request (restricted to the batched kernel's instances).
-fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho, int wo,
-                                    FwdGeom* g);
+fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho,
+                                    int wo, FwdGeom* g);
 
 // Channel-mixing launchers (mix4.hip); dtype FCFS_BF16 or FCFS_F16.
 fcfs_status launch_mix4(int dtype, const MixArgs& a, hipStream_t stream);
@@ -148,7 +160,7 @@ fcfs_status launch_forward_bf16(int method, const FwdArgs& a, const FwdGeom& g, 
 fcfs_status launch_forward_f16(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);
 
 // Host-side launch geometry for a plane of (h, w) -> (ho, wo).
-fcfs_status plan_forward_geom(const fcfs_plan_* plan, int64_t planes, int h, int w, int ho,
+fcfs_status plan_forward_geom(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho,
                               int wo, bool pair_ok, FwdGeom* g);
 
 }  // namespace fcfs

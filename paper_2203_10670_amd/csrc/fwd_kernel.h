@@ -53,6 +53,7 @@ constexpr int kPrefetch = FCFS_FWD_PREFETCH;   // rows in flight per wave
 constexpr int kXcds = 8;        // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // ---------------------------------------------------------------- storage types
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <int DT> struct Store;
 template <> struct Store<FCFS_F32> {
   using T = float;
@@ -64,35 +65,42 @@ template <> struct Store<FCFS_F32> {
 };
 template <> struct Store<FCFS_BF16> {
   using T = uint16_t;
+  typedef __bf16 x2 __attribute__((ext_vector_type(2)));
   static __device__ __forceinline__ float from_bits(uint32_t b) { return __uint_as_float(b << 16); }
-  static __device__ __forceinline__ uint32_t to_bits(float v) {
-    const uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // quiet NaN
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;                     // round to nearest even
-  }
   static __device__ __forceinline__ float load(const T* p) {
     const uint32_t b = *p;
     return __uint_as_float(b << 16);
   }
+  // round to nearest even (NaN stays a quiet NaN)
   static __device__ __forceinline__ void store(T* p, float v) {
-    const uint32_t u = __float_as_uint(v);
-    uint16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) r = (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
-    else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);               // round to nearest even
+    const T r = __builtin_bit_cast(T, (__bf16)v);
     if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store(r, p);
     else *p = r;
+  }
+  // p[0] = lo, p[1] = hi (p 4-byte aligned)
+  static __device__ __forceinline__ void store2(T* p, float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    const uint32_t r = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, x2));
+    if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store(r, reinterpret_cast<uint32_t*>(p));
+    else *reinterpret_cast<uint32_t*>(p) = r;
   }
 };
 template <> struct Store<FCFS_F16> {
   using T = _Float16;
+  typedef _Float16 x2 __attribute__((ext_vector_type(2)));
   static __device__ __forceinline__ float from_bits(uint32_t b) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
   }
-  static __device__ __forceinline__ uint32_t to_bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
   static __device__ __forceinline__ float load(const T* p) { return (float)*p; }
   static __device__ __forceinline__ void store(T* p, float v) {
     if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store((_Float16)v, p);
     else *p = (_Float16)v;
+  }
+  static __device__ __forceinline__ void store2(T* p, float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    const uint32_t r = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, x2));
+    if (FCFS_FWD_NT_STORE) __builtin_nontemporal_store(r, reinterpret_cast<uint32_t*>(p));
+    else *reinterpret_cast<uint32_t*>(p) = r;
   }
 };
 
@@ -123,11 +131,22 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Input column the strip of wave `wid` stages first, aligned down to an even
+// column in paired mode.
+template <bool PAIR>
+__device__ __forceinline__ int strip_first_column(const FwdArgs& a, int64_t wid) {
+  const AxisTable& TW = a.tw_tab;
+  const int ow0 = (int)(wid % a.strips) * a.tw;
+  const int c = TW.q * (ow0 / TW.p) + TW.omin;
+  return PAIR ? (c & ~1) : c;
+}
+
 // The per-wave work of the forward: wave `wid` of the launch described by `a`
 // (a may live in the kernel-argument segment or in device memory).
-// PAIR (16-bit storage, even widths, 4-byte aligned tensors): every lane
-// loads and stores two adjacent samples as one dword; its output columns are
-// adjacent pairs ow0 + 2*lane + 128*g + {0, 1}.
+// PAIR (16-bit storage, even widths, 4-byte aligned tensors, and a staged
+// segment wholly inside the row): every lane loads and stores two adjacent
+// samples as one dword; its output columns are the adjacent pairs
+// ow0 + 2*lane + 128*g + {0, 1}.
 template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false>
 __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslot, int lane, float* smem) {
   using S = Store<DT>;
@@ -145,10 +164,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   const int owEnd = min(ow0 + a.tw, a.Wo);
   const int m0 = band * a.band_cells;
   const int m1 = min(m0 + a.band_cells, a.Mh);
-
-  const int n0 = ow0 / TW.p;
-  // first input column staged (even in paired mode, so pairs are aligned)
-  const int cs = PAIR ? ((TW.q * n0 + TW.omin) & ~1) : TW.q * n0 + TW.omin;
+  const int cs = strip_first_column<PAIR>(a, wid);
 
   float* row = smem + wslot * kRowMax;
   float* wl = nullptr;
@@ -181,69 +197,51 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
     for (int b = 0; b < T; ++b) wc[c][b] = LEARNED ? 0.f : TW.w[jw][b];
   }
 
-  // Source column of each staged slot lane + 64*s, clamped into the row;
-  // ckeep = false where zero padding supplies the value. Paired: slot s holds
-  // columns cs + 2*(lane + 64*s) + {0, 1}; pairs wholly inside the row load as
-  // one dword, the others (edge strips only) fetch each sample on its own.
-  constexpr int E = PAIR ? 2 : 1;
-  int scol[L][E];
-  bool ckeep[L][E];
-  int pcol[L];
-  bool pin[L];
+  // Source column of staged slot s of this lane (single samples: column
+  // cs + lane + 64*s, clamped into the row, ckeep = false where zero padding
+  // supplies the value; pairs: columns cs + 2*(lane + 64*s) + {0, 1}, inside
+  // the row by construction).
+  int scol[L];
+  bool ckeep[L];
 #pragma unroll
   for (int s = 0; s < L; ++s) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int src = pad_source(cs + E * (lane + 64 * s) + e, a.W, a.pad);
-      ckeep[s][e] = src >= 0;
-      scol[s][e] = src >= 0 ? src : 0;
+    if constexpr (PAIR) {
+      scol[s] = cs + 2 * (lane + 64 * s);
+      ckeep[s] = true;
+    } else {
+      const int src = pad_source(cs + lane + 64 * s, a.W, a.pad);
+      ckeep[s] = src >= 0;
+      scol[s] = src >= 0 ? src : 0;
     }
-    const int c0 = cs + 2 * (lane + 64 * s);
-    pin[s] = PAIR && c0 >= 0 && c0 + 1 < a.W;
-    pcol[s] = pin[s] ? c0 : 0;
   }
-  bool edge = false;
-  if constexpr (PAIR) edge = cs < 0 || cs + 128 * L > a.W;   // some pair leaves the row
 
   const TS* xplane = reinterpret_cast<const TS*>(a.x) + plane * (int64_t)a.H * a.W;
   TS* yplane = reinterpret_cast<TS*>(a.y) + plane * (int64_t)a.Ho * a.Wo;
 
+  // Band rows rs..re, streamed top to bottom. A row no tap reads (nearest,
+  // large q) is replaced by the nearest row below that one does (already
+  // fetched: a cache hit); fetches past re repeat the last row.
   const int rs = TH.q * m0 + TH.omin;
   const int re = TH.q * (m1 - 1) + TH.omax;
-
-  // Input row fetched for band row r: r itself when some tap reads it, else
-  // the nearest such row below (already fetched); rows past the band end
-  // repeat its last row. Returns the source row, or -1 for a zero row.
-  auto fetch_row = [&](int r) -> int {
-    r = min(r, re);
-    r -= TH.back[mod_pos(r, TH.q)];
-    return pad_source(r, a.H, a.pad);
-  };
+  auto source_row = [&](int r, int r_mod_q) -> int { return pad_source(r - TH.back[r_mod_q], a.H, a.pad); };
+  const int src_last = source_row(re, mod_pos(re, TH.q));
 
   // prefetched rows: FP32 values, or raw sample pairs in paired mode
   using Raw = typename std::conditional<PAIR, uint32_t, float>::type;
   Raw buf[kPrefetch][L];
-  uint32_t fix[kPrefetch][PAIR ? L : 1];   // edge pairs assembled sample by sample
-  int bsrc[kPrefetch];
-  auto load_row = [&](int r, Raw (&dst)[L], uint32_t (&fx)[PAIR ? L : 1], int& src_out) {
-    const int sr = fetch_row(r);
+  int bsrc[kPrefetch];   // source row of each slot, -1 for a zero row
+  int fr = rs, frho = mod_pos(rs, TH.q);   // next row to fetch, and it mod q
+  auto fetch_next = [&](Raw (&dst)[L], int& src_out) __attribute__((always_inline)) {
+    const int sr = fr <= re ? source_row(fr, frho) : src_last;
     src_out = sr;
     const TS* src = xplane + (int64_t)(sr < 0 ? 0 : sr) * a.W;
-    if constexpr (PAIR) {
 #pragma unroll
-      for (int s = 0; s < L; ++s) dst[s] = *reinterpret_cast<const uint32_t*>(src + pcol[s]);
-      if (edge) {
-#pragma unroll
-        for (int s = 0; s < L; ++s) {
-          const uint32_t lo = *reinterpret_cast<const uint16_t*>(src + scol[s][0]);
-          const uint32_t hi = *reinterpret_cast<const uint16_t*>(src + scol[s][1]);
-          fx[s] = lo | (hi << 16);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < L; ++s) dst[s] = S::load(src + scol[s][0]);
+    for (int s = 0; s < L; ++s) {
+      if constexpr (PAIR) dst[s] = *reinterpret_cast<const uint32_t*>(src + scol[s]);
+      else dst[s] = S::load(src + scol[s]);
     }
+    ++fr;
+    frho = (frho + 1 == TH.q) ? 0 : frho + 1;
   };
 
   // FIFO of the last T rows: fixed methods keep the width-filtered value per
@@ -258,105 +256,116 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
       for (int b = 0; b < FT; ++b) fifo[c][t][b] = 0.f;
 
 #pragma unroll
-  for (int d = 0; d < kPrefetch; ++d) load_row(rs + d, buf[d], fix[d], bsrc[d]);
+  for (int d = 0; d < kPrefetch; ++d) fetch_next(buf[d], bsrc[d]);
 
-  int rho = mod_pos(rs, TH.q);
-  for (int rb = rs; rb <= re; rb += kPrefetch) {
+  int rho = mod_pos(rs, TH.q);     // row being processed, mod q
+  int rq = (rs - rho) / TH.q;      // ... and divided by q (floor)
+
+  // One band row from prefetch slot d (a compile-time constant once unrolled).
+  auto step = [&](const int d) __attribute__((always_inline)) {
+    // stage the row (zero padding applied here), then refill the slot
+    const bool zrow = bsrc[d] < 0;
+    if constexpr (PAIR) {
 #pragma unroll
-    for (int d = 0; d < kPrefetch; ++d) {
-      const int r = rb + d;
-      if (r > re) break;
-      // stage the row (zero padding applied here), then refill the slot
-      const bool zrow = bsrc[d] < 0;
-      if constexpr (PAIR) {
+      for (int s = 0; s < L; ++s) {
+        const uint32_t raw = buf[d][s];
+        row[2 * (lane + 64 * s)] = zrow ? 0.f : S::from_bits(raw & 0xffffu);
+        row[2 * (lane + 64 * s) + 1] = zrow ? 0.f : S::from_bits(raw >> 16);
+      }
+    } else {
 #pragma unroll
-        for (int s = 0; s < L; ++s) {
-          const uint32_t raw = (edge && !pin[s]) ? fix[d][s] : buf[d][s];
-          row[2 * (lane + 64 * s)] = (ckeep[s][0] && !zrow) ? S::from_bits(raw & 0xffffu) : 0.f;
-          row[2 * (lane + 64 * s) + 1] = (ckeep[s][1] && !zrow) ? S::from_bits(raw >> 16) : 0.f;
+      for (int s = 0; s < L; ++s) row[lane + 64 * s] = (ckeep[s] && !zrow) ? buf[d][s] : 0.f;
+    }
+    fetch_next(buf[d], bsrc[d]);
+    wave_lds_sync();
+    float cur[KC][FT];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      if constexpr (LEARNED) {
+#pragma unroll
+        for (int b = 0; b < T; ++b) cur[c][b] = row[pos[c] + b];
+      } else if constexpr (T == 1) {
+        cur[c][0] = row[pos[c]];
+      } else {
+        float h = wc[c][0] * row[pos[c]];
+#pragma unroll
+        for (int b = 1; b < T; ++b) h = __builtin_fmaf(wc[c][b], row[pos[c] + b], h);
+        cur[c][0] = h;
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+#pragma unroll
+      for (int t = 0; t + 1 < T; ++t)
+#pragma unroll
+        for (int b = 0; b < FT; ++b) fifo[c][t][b] = fifo[c][t + 1][b];
+#pragma unroll
+      for (int b = 0; b < FT; ++b) fifo[c][T - 1][b] = cur[c][b];
+    }
+
+    // Finish every output row whose last height tap is this row.
+    const int e1 = TH.emit_start[rho + 1];
+    for (int e = TH.emit_start[rho]; e < e1; ++e) {
+      const EmitRec er = a.emit[e];
+      const int m = rq - er.lag;
+      if (m < m0 || m >= m1) continue;
+      TS* orow = yplane + (int64_t)(TH.p * m + er.j) * a.Wo;
+      float outv[KC];
+      if constexpr (LEARNED) {
+        const float* wj = wl + er.j * TW.p * 16;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          const float* wk = wj + wbase[c];
+          float acc = 0.f;
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int b = 0; b < T; ++b) acc = __builtin_fmaf(wk[t * 4 + b], fifo[c][t][b], acc);
+          outv[c] = acc;
         }
+      } else if constexpr (T == 1) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) outv[c] = fifo[c][0][0];
       } else {
 #pragma unroll
-        for (int s = 0; s < L; ++s) row[lane + 64 * s] = (ckeep[s][0] && !zrow) ? buf[d][s] : 0.f;
-      }
-      load_row(r + kPrefetch, buf[d], fix[d], bsrc[d]);
-      wave_lds_sync();
-      float cur[KC][FT];
+        for (int c = 0; c < KC; ++c) {
+          float acc = er.w[0] * fifo[c][0][0];
 #pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        if constexpr (LEARNED) {
-#pragma unroll
-          for (int b = 0; b < T; ++b) cur[c][b] = row[pos[c] + b];
-        } else if constexpr (T == 1) {
-          cur[c][0] = row[pos[c]];
-        } else {
-          float h = wc[c][0] * row[pos[c]];
-#pragma unroll
-          for (int b = 1; b < T; ++b) h = __builtin_fmaf(wc[c][b], row[pos[c] + b], h);
-          cur[c][0] = h;
+          for (int t = 1; t < T; ++t) acc = __builtin_fmaf(er.w[t], fifo[c][t][0], acc);
+          outv[c] = acc;
         }
       }
-      wave_lds_sync();
+      if constexpr (PAIR) {
+        // both columns of a pair are valid or neither (even widths and starts)
 #pragma unroll
-      for (int c = 0; c < KC; ++c) {
+        for (int g = 0; g < KC / 2; ++g)
+          if (cvalid[2 * g]) S::store2(orow + ocol[2 * g], outv[2 * g], outv[2 * g + 1]);
+      } else {
 #pragma unroll
-        for (int t = 0; t + 1 < T; ++t)
-#pragma unroll
-          for (int b = 0; b < FT; ++b) fifo[c][t][b] = fifo[c][t + 1][b];
-#pragma unroll
-        for (int b = 0; b < FT; ++b) fifo[c][T - 1][b] = cur[c][b];
+        for (int c = 0; c < KC; ++c)
+          if (cvalid[c]) S::store(orow + ocol[c], outv[c]);
       }
-
-      // Finish every output row whose last height tap is input row r.
-      const int e1 = TH.emit_start[rho + 1];
-      for (int e = TH.emit_start[rho]; e < e1; ++e) {
-        const int j = TH.emit_list[e];
-        const int m = (r - (TH.off[j] + T - 1)) / TH.q;   // exact: r = last tap (mod q)
-        if (m < m0 || m >= m1) continue;
-        TS* orow = yplane + (int64_t)(TH.p * m + j) * a.Wo;
-        float outv[KC];
-        if constexpr (LEARNED) {
-          const float* wj = wl + j * TW.p * 16;
-#pragma unroll
-          for (int c = 0; c < KC; ++c) {
-            const float* wk = wj + wbase[c];
-            float acc = 0.f;
-#pragma unroll
-            for (int t = 0; t < T; ++t)
-#pragma unroll
-              for (int b = 0; b < T; ++b) acc = __builtin_fmaf(wk[t * 4 + b], fifo[c][t][b], acc);
-            outv[c] = acc;
-          }
-        } else if constexpr (T == 1) {
-#pragma unroll
-          for (int c = 0; c < KC; ++c) outv[c] = fifo[c][0][0];
-        } else {
-          float wv[T];
-#pragma unroll
-          for (int t = 0; t < T; ++t) wv[t] = TH.w[j][t];
-#pragma unroll
-          for (int c = 0; c < KC; ++c) {
-            float acc = wv[0] * fifo[c][0][0];
-#pragma unroll
-            for (int t = 1; t < T; ++t) acc = __builtin_fmaf(wv[t], fifo[c][t][0], acc);
-            outv[c] = acc;
-          }
-        }
-        if constexpr (PAIR) {
-          // both columns of a pair are valid or neither (even widths and starts)
-#pragma unroll
-          for (int g = 0; g < KC / 2; ++g)
-            if (cvalid[2 * g])
-              __builtin_nontemporal_store(S::to_bits(outv[2 * g]) | (S::to_bits(outv[2 * g + 1]) << 16),
-                                          reinterpret_cast<uint32_t*>(orow + ocol[2 * g]));
-        } else {
-#pragma unroll
-          for (int c = 0; c < KC; ++c)
-            if (cvalid[c]) S::store(orow + ocol[c], outv[c]);
-        }
-      }
-      rho = (rho + 1 == TH.q) ? 0 : rho + 1;
     }
+    if (++rho == TH.q) {
+      rho = 0;
+      ++rq;
+    }
+  };
+
+  // Whole groups of kPrefetch rows, then the remainder. (Keeping the partial
+  // group out of the loop lets every wait on a prefetched row count the three
+  // younger rows' loads as still in flight.)
+  const int nrows = re - rs + 1;
+  for (int g = nrows / kPrefetch; g > 0; --g) {
+#pragma unroll
+    for (int d = 0; d < kPrefetch; ++d) step(d);
+  }
+  const int tail = nrows % kPrefetch;
+#pragma unroll
+  for (int d = 0; d + 1 < kPrefetch; ++d) {
+    if (d >= tail) break;
+    step(d);
   }
 }
 
@@ -377,7 +386,15 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   }
   const int64_t wid = blk * kWaves + wslot;
   if (wid >= a.waves) return;
-  fwd_wave<DT, T, KC, L, LEARNED, PAIR>(a, wid, wslot, lane, smem);
+  if constexpr (PAIR) {
+    // strips whose staged segment reaches past either end of the row (and so
+    // needs padding) move single samples
+    const int cs = strip_first_column<true>(a, wid);
+    if (cs < 0 || cs + 128 * L > a.W) fwd_wave<DT, T, KC, 2 * L, LEARNED, false>(a, wid, wslot, lane, smem);
+    else fwd_wave<DT, T, KC, L, LEARNED, true>(a, wid, wslot, lane, smem);
+  } else {
+    fwd_wave<DT, T, KC, L, LEARNED, false>(a, wid, wslot, lane, smem);
+  }
 }
 
 template <int DT, int T, int KC, bool LEARNED>

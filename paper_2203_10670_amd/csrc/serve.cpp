@@ -301,8 +301,9 @@ void scheduler_loop(fcfs_server_* s) {
       a.pad = t.plan->pad;
       a.th = t.plan->ah;
       a.tw_tab = t.plan->aw;
+      fill_emit(t.plan->ah, a.emit);
       FwdGeom g;
-      plan_forward_geom_batch(t.plan, a.planes, a.H, a.W, a.Ho, a.Wo, &g);
+      plan_forward_geom_batch(t.plan, t.req.dtype, a.planes, a.H, a.W, a.Ho, a.Wo, &g);
       a.tw = g.tw;
       a.strips = g.strips;
       a.band_cells = g.band_cells;

@@ -7,6 +7,7 @@ import glob
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -139,3 +140,15 @@ def test_server_needs_a_device():
     assert e.value.status in (fc.E_DEVICE, fc.E_NOMEM)
     h = ctypes.c_void_p()
     assert fc.lib.fcfs_server_create(0, 1 << 20, 0, ctypes.byref(h)) == fc.E_INVAL
+
+
+def test_one_hip_runtime_with_torch():
+    # importing the package before torch must not bring a second HIP runtime
+    # into the process (the library binds to the one torch uses)
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2203_10670_amd, torch\n"
+            "libs = set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)\n"
+            "print(len(libs), sorted(libs))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("1 "), out.stdout
