@@ -374,7 +374,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and lib is not None:   # (module globals may be gone at interpreter exit)
             lib.fcfs_plan_destroy(h)
             self.handle = None
 

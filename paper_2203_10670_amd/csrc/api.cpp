@@ -401,25 +401,53 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   a.pad = plan->pad;
   a.th = plan->ah;
   a.tw_tab = plan->aw;
-  a.tw_cells = 32;
-  a.th_cells = 4;
-  a.tiles_h = (a.Mh + a.th_cells - 1) / a.th_cells;
-  a.tiles_w = (a.Mw + a.tw_cells - 1) / a.tw_cells;
-  a.groups = (plan->aw.p + 4) / 5;
-  a.otiles = (int)((c_out + 63) / 64);
-  const int P = std::min(5, plan->aw.p);
-  const int R = plan->ah.q * (a.th_cells - 1) + 4;
+  const int P = std::min(5, plan->aw.p);   // width phases per group
+  a.gsize = P;
+  a.groups = (plan->aw.p + P - 1) / P;
+  a.otiles = (int)((c_out + 31) / 32);
   int spread = 0;
   for (int g = 0; g < a.groups; ++g) {
-    const int j0 = g * 5, j1 = std::min(plan->aw.p, j0 + 5) - 1;
+    const int j0 = g * P, j1 = std::min(plan->aw.p, j0 + P) - 1;
     spread = std::max(spread, plan->aw.off[j1] - plan->aw.off[j0]);
   }
-  const int Cc = (plan->aw.q * (a.tw_cells - 1) + spread + 4 + 1) & ~1;
-  const size_t stage = ((2 * sizeof(uint16_t) * (size_t)R * Cc + 15) & ~(size_t)15) + sizeof(uint16_t) * (size_t)P * 64 * 2 * 16;
-  const size_t epi = sizeof(uint16_t) * 16 * (size_t)a.th_cells * a.tw_cells * P;
-  const size_t lds = std::max(stage, epi) + 16;
-  if (lds > 65536) return FCFS_E_UNSUPPORTED;
-  a.lds_bytes = (int)lds;
+  // Cell tile: 128 cells. The first shape whose staged patch travels in
+  // registers (at most 8 (channel, row) pairs per wave and 3 column slots of
+  // 64) with two stage buffers in 64 KB of LDS (the pipelined kernel); else
+  // the first whose one buffer fits (the kernel that stages between steps).
+  const int qh = plan->ah.q, qw = plan->aw.q;
+  const int wspan = spread + 4;
+  static const int shapes[][2] = {{4, 32}, {8, 16}, {2, 64}, {16, 8}, {1, 128}, {32, 4}, {64, 2}, {128, 1}};
+  bool found = false;
+  for (int pass = 0; pass < 2 && !found; ++pass) {
+    for (const auto& sh : shapes) {
+      MixArgs t = a;
+      t.th_cells = sh[0];
+      t.tw_cells = sh[1];
+      t.rstep = std::min(qh, 4);
+      t.R = t.rstep * (t.th_cells - 1) + 4;
+      t.wspan = wspan;
+      t.cstep = qw < wspan ? qw : wspan;
+      t.Cc = t.cstep * (t.tw_cells - 1) + wspan;
+      t.CP = (t.Cc + 1) | 1;   // a spare column; odd pitch: neighbouring rows start in different banks
+      t.npr = (2 * t.R + 3) / 4;
+      t.ncs = (t.Cc + 63) / 64;
+      t.items = t.npr * t.ncs;
+      t.woff_u16 = (2 * t.R * t.CP + 7) & ~7;
+      t.buf_u16 = t.woff_u16 + P * 32 * 32 + 8;   // + a spare quad
+      t.nbuf = pass == 0 ? 2 : 1;
+      const size_t epi = sizeof(uint16_t) * 16 * (size_t)t.th_cells * t.tw_cells * P;
+      const size_t lds = std::max(sizeof(uint16_t) * t.nbuf * (size_t)t.buf_u16, epi);
+      const bool regs = t.npr <= 8 && t.ncs <= 3;
+      if (lds > 65536 || (pass == 0 && !regs)) continue;
+      t.lds_bytes = (int)lds;
+      a = t;
+      found = true;
+      break;
+    }
+  }
+  if (!found) return FCFS_E_UNSUPPORTED;
+  a.tiles_h = (a.Mh + a.th_cells - 1) / a.th_cells;
+  a.tiles_w = (a.Mw + a.tw_cells - 1) / a.tw_cells;
   const int64_t blocks = n * (int64_t)a.tiles_h * a.tiles_w * plan->ah.p * a.groups * a.otiles;
   if (blocks >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
   return launch_mix4(dtype, a, stream);

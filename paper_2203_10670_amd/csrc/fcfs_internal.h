@@ -105,9 +105,20 @@ struct MixArgs {
   int N, Cin, Cout;
   int H, W, Ho, Wo, Mh, Mw;
   int pad;
-  int th_cells, tw_cells;    // cell tile of a workgroup
+  int th_cells, tw_cells;    // cell tile of a workgroup (th_cells * tw_cells = 128)
   int tiles_h, tiles_w, groups, otiles;
+  int gsize;                 // width phases per group: min(5, p_w)
   int lds_bytes;
+  // staged input patch of a workgroup, per input channel: R rows x Cc columns
+  // (row pitch CP); cell (lh, lw) tap (a, b) of width phase jw sits at row
+  // rstep*lh + a, column cstep*lw + off_w[jw] - off_w[first phase] + b
+  int R, Cc, CP;
+  int rstep, cstep;          // = q (all rows/columns staged) or 4 / wspan (only the tapped ones)
+  int wspan;                 // columns a cell's taps cover over the phase group
+  int npr, ncs, items;       // (channel, row) pairs per wave, 64-column slots per row, items per lane
+  int nbuf;                  // LDS stage buffers (2, or 1 when two do not fit)
+  int buf_u16, woff_u16;     // LDS stage buffer size and weight offset in it (16-bit units):
+                             // patch [2][R][CP], then weights [gsize][32][32] and a spare quad
   AxisTable th, tw_tab;
 };
 

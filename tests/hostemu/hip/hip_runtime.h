@@ -52,6 +52,7 @@ inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); retu
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 #define __builtin_amdgcn_readfirstlane(x) (x)
 #define __builtin_amdgcn_fence(...) ((void)0)
+#define __builtin_amdgcn_sched_barrier(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() (hostemu::wave_bar_->arrive_and_wait())
 #define __syncthreads() (hostemu::block_bar_->arrive_and_wait())
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))

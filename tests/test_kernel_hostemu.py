@@ -121,6 +121,11 @@ def test_channel_mixing_mfma():
                           "cout": 5})
     cases.append({"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "bf16", "shape": [2, 4, 9, 150],
                   "cout": 70})
+    # large q (only the tapped rows and columns are staged) and an odd channel count
+    cases.append({"p": 2, "q": 7, "method": "mix4", "pad": "reflect", "dtype": "bf16", "shape": [1, 5, 30, 60],
+                  "cout": 3})
+    cases.append({"p": 9, "q": 8, "method": "mix4", "pad": "replicate", "dtype": "f16", "shape": [1, 3, 20, 75],
+                  "cout": 4})
     cases.append({"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 2, 8, 8],
                   "cout": 2, "expect_status": 2})
     _run(cases)
