@@ -404,7 +404,7 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   const int P = std::min(5, plan->aw.p);   // width phases per group
   a.gsize = P;
   a.groups = (plan->aw.p + P - 1) / P;
-  a.otiles = (int)((c_out + 31) / 32);
+  a.otiles = (int)((c_out + kMixOut - 1) / kMixOut);
   int spread = 0;
   for (int g = 0; g < a.groups; ++g) {
     const int j0 = g * P, j1 = std::min(plan->aw.p, j0 + P) - 1;
@@ -433,7 +433,7 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
       t.ncs = (t.Cc + 63) / 64;
       t.items = t.npr * t.ncs;
       t.woff_u16 = (2 * t.R * t.CP + 7) & ~7;
-      t.buf_u16 = t.woff_u16 + P * 32 * 32 + 8;   // + a spare quad
+      t.buf_u16 = t.woff_u16 + P * kMixOut * 32 + 8;   // + a spare quad
       t.nbuf = pass == 0 ? 2 : 1;
       const size_t epi = sizeof(uint16_t) * 16 * (size_t)t.th_cells * t.tw_cells * P;
       const size_t lds = std::max(sizeof(uint16_t) * t.nbuf * (size_t)t.buf_u16, epi);

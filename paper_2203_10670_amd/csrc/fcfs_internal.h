@@ -98,6 +98,8 @@ struct BwdArgs {
   AxisTable th, tw_tab;
 };
 
+constexpr int kMixOut = 32;   // output channels per channel-mixing workgroup
+
 struct MixArgs {
   const void* x;         // [N][Cin][H][W], 16-bit storage
   const void* w;         // [p_h][p_w][Cout][Cin][4][4], same storage type, 16-byte aligned

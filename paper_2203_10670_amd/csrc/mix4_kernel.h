@@ -6,20 +6,19 @@
 // [q_w*mw + off_w[jw] + b], i.e. rows M = cells (n, mh, mw), columns N = o,
 // reduction K = (c, a, b) with k = 16c + 4a + b.
 //
-// Workgroup: 4 waves, 128 cells (th_cells x tw_cells), 32 output channels,
+// Workgroup: 4 waves, 128 cells (th_cells x tw_cells), kOut output channels,
 // one height phase jh and a group of up to kGroup width phases, which share
 // the staged input patch. The K loop takes two input channels per step (one
 // MFMA K-step of 32). Each step's patch (2 channels) and weights (the group's
-// phases x 32 outputs x 32 k) sit in one of two LDS buffers: while the waves
+// phases x kOut outputs x 32 k) sit in one of two LDS buffers: while the waves
 // run the step's MFMAs from one buffer, the next step's data is already on
 // its way into registers, and is written to the other buffer afterwards, so
 // one barrier per step orders everything and the global-memory latency hides
 // behind the matrix work. (When two buffers do not fit, one buffer and a
 // second barrier per step.)
 //
-// Wave tile: 32 cells x 32 channels per phase, v_mfma_f32_16x16x32 (bf16 or
-// f16), FP32 accumulation (80 accumulator registers, so two workgroups fit on
-// a compute unit and cover each other's waits). The epilogue stages 16 output channels at a time
+// Wave tile: 32 cells x kOut channels per phase, v_mfma_f32_16x16x32 (bf16
+// or f16), FP32 accumulation. The epilogue stages 16 output channels at a time
 // in LDS and writes whole output row segments.
 //
 // Operand layouts of v_mfma_f32_16x16x32_{bf16,f16} (checked on the device):
@@ -39,7 +38,7 @@ using fwd::pad_source;
 
 constexpr int kThreads = 256;
 constexpr int kGroup = 5;      // width phases per workgroup, at most
-constexpr int kOut = 32;       // output channels per workgroup
+constexpr int kOut = kMixOut;  // output channels per workgroup
 constexpr int kWPitch = 32;    // 16-bit units per (phase, output) weight row in LDS (2 channels x 16 taps);
                                // its four 16-byte quads are stored rotated by ((o >> 1) & 3), so the
                                // 16-byte reads of 8 consecutive outputs hit distinct banks
@@ -117,9 +116,9 @@ __global__ __launch_bounds__(kThreads) void mix4_kernel(const MixArgs a) {
     const int r = a.rstep == TH.q ? r0 + rr : r0 + TH.q * (rr >> 2) + (rr & 3);
     return pad_source(r, a.H, a.pad);
   };
-  // weights: 16-byte quads (phase, output, quad) = it / 128, (it / 4) % 32,
-  // it % 4 (an output's 2 channels x 16 taps are 4 quads); thread t moves
-  // items t, t + 256, t + 512; items past G * 128 go to a spare quad
+  // weights: 16-byte quads (phase, output, quad) = it / (4 kOut),
+  // (it / 4) % kOut, it % 4 (an output's 2 channels x 16 taps are 4 quads);
+  // thread t moves items t, t + 256, ...; items past 4 G kOut go to a spare quad
   const uint16_t* win = reinterpret_cast<const uint16_t*>(a.w);
   constexpr int kWItems = (G * kOut * 4 + kThreads - 1) / kThreads;
   int64_t woff[kWItems];
@@ -136,10 +135,15 @@ __global__ __launch_bounds__(kThreads) void mix4_kernel(const MixArgs a) {
     woff[k] = ok ? ((((int64_t)jh * TW.p + jw0 + ph) * a.Cout + o0 + o) * a.Cin) * 16 + quad * 8 : 0;
     wlds[k] = ph < G ? (ph * kOut + o) * kWPitch + (quad ^ ((o >> 1) & 3)) * 8 : G * kOut * kWPitch;
   }
+  // (the mask is applied where the quad is stored, so that the load itself
+  // stays in flight until then)
   auto load_w = [&](int k, int cc) -> uint4 {
+    const bool ok = wmask[k] && cc + wch_hi[k] < a.Cin;
+    return *reinterpret_cast<const uint4*>(win + (ok ? woff[k] + cc * 16 : 0));
+  };
+  auto mask_w = [&](int k, int cc, uint4 v) -> uint4 {
     // quads 2 and 3 hold channel cc + 1, which may be past C_in
     const uint32_t m = cc + wch_hi[k] < a.Cin ? wmask[k] : 0u;
-    const uint4 v = *reinterpret_cast<const uint4*>(win + (m ? woff[k] + cc * 16 : 0));
     return uint4{v.x & m, v.y & m, v.z & m, v.w & m};
   };
 
@@ -192,60 +196,80 @@ __global__ __launch_bounds__(kThreads) void mix4_kernel(const MixArgs a) {
 
   const int nsteps = (a.Cin + 1) / 2;
   if constexpr (FAST) {
-    int scol[kSlotsFast];
-    uint32_t cmask[kSlotsFast];
+    // Per-lane plan of the patch items: byte offset of (row, column) in a
+    // channel plane, and one bit per item, set unless zero padding supplies
+    // it. Tiles clear of the image border under zero padding (and every tile
+    // under replicate or reflect padding) load without masks.
+    const int64_t plane = (int64_t)a.H * a.W;
+    uint32_t ioff[kRowsFast][kSlotsFast];
+    uint32_t vbits = 0;
 #pragma unroll
     for (int j = 0; j < kSlotsFast; ++j) {
       const int pc = lane + 64 * j;
       const int sc = pc < a.Cc ? src_col(pc) : -1;
-      cmask[j] = sc >= 0 ? 0xffffu : 0u;
-      scol[j] = sc >= 0 ? sc : 0;
-    }
-    uint32_t pre[kRowsFast][kSlotsFast];
-    uint4 wpre[kWItems];
-    auto load_step = [&](int cc) {
 #pragma unroll
       for (int i = 0; i < kRowsFast; ++i) {
         const int pr = wave + 4 * i;
         const int ch = pr >= a.R ? 1 : 0;
-        const int sr = src_row(pr - ch * a.R);
-        const bool rok = pr < 2 * a.R && cc + ch < a.Cin && sr >= 0;
-        const uint16_t* rowp = xin + ((int64_t)(rok ? cc + ch : 0) * a.H + (rok ? sr : 0)) * a.W;
-        const uint32_t rm = rok ? 0xffffu : 0u;
+        const int sr = pr < 2 * a.R ? src_row(pr - ch * a.R) : -1;
+        const bool ok = sr >= 0 && sc >= 0;
+        ioff[i][j] = 2u * (uint32_t)((ok ? sr : 0) * a.W + (ok ? sc : 0));   // bytes
+        vbits |= (ok ? 1u : 0u) << (i * kSlotsFast + j);
+      }
+    }
+    const int rlast = a.rstep == TH.q ? r0 + a.R - 1 : r0 + TH.q * (a.th_cells - 1) + 3;
+    const int clast = a.cstep == TW.q ? c0 + a.Cc - 1 : c0 + TW.q * (a.tw_cells - 1) + a.wspan - 1;
+    const bool masked = a.pad == FCFS_PAD_ZERO && (r0 < 0 || rlast >= a.H || c0 < 0 || clast >= a.W);
+
+    uint32_t pre[kRowsFast][kSlotsFast];
+    uint4 wpre[kWItems];
+    // loads of a step: raw values; the masks apply when they are stored
+    auto load_step = [&](int cc) {
+      const uint16_t* b0 = xin + (int64_t)cc * plane;
+      const uint16_t* b1 = cc + 1 < a.Cin ? b0 + plane : b0;
 #pragma unroll
-        for (int j = 0; j < kSlotsFast; ++j) {
-          // unconditional load (clamped row and column), masked afterwards, so
-          // that it stays in flight through the step's MFMAs
-          const uint32_t v = rowp[scol[j]];
-          pre[i][j] = v & rm & cmask[j];
-        }
+      for (int i = 0; i < kRowsFast; ++i) {
+        const char* b = reinterpret_cast<const char*>(wave + 4 * i >= a.R ? b1 : b0);
+#pragma unroll
+        for (int j = 0; j < kSlotsFast; ++j) pre[i][j] = *reinterpret_cast<const uint16_t*>(b + ioff[i][j]);
       }
 #pragma unroll
       for (int k = 0; k < kWItems; ++k) wpre[k] = load_w(k, cc);
     };
-    auto store_step = [&](uint16_t* patch) {
+    auto store_step = [&](uint16_t* patch, int cc, bool mask) {
+      const uint32_t m1 = cc + 1 < a.Cin ? 0xffffu : 0u;   // the step's second channel may be past C_in
 #pragma unroll
       for (int i = 0; i < kRowsFast; ++i) {
         const int pr = wave + 4 * i;
         if (pr >= 2 * a.R) break;
 #pragma unroll
-        for (int j = 0; j < kSlotsFast; ++j) patch[pr * a.CP + min(lane + 64 * j, a.Cc)] = (uint16_t)pre[i][j];
+        for (int j = 0; j < kSlotsFast; ++j) {
+          uint32_t v = pre[i][j];
+          if (pr >= a.R) v &= m1;
+          if (mask) v &= ((vbits >> (i * kSlotsFast + j)) & 1u) ? 0xffffu : 0u;
+          patch[pr * a.CP + min(lane + 64 * j, a.Cc)] = (uint16_t)v;
+        }
       }
       uint16_t* wch = patch + a.woff_u16;
 #pragma unroll
-      for (int k = 0; k < kWItems; ++k) *reinterpret_cast<uint4*>(wch + wlds[k]) = wpre[k];
+      for (int k = 0; k < kWItems; ++k) *reinterpret_cast<uint4*>(wch + wlds[k]) = mask_w(k, cc, wpre[k]);
     };
-
-    load_step(0);
-    store_step(lds);
-    __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-      uint16_t* cur = lds + (s & 1) * a.buf_u16;
-      if (s + 1 < nsteps) load_step(2 * (s + 1));
-      compute(cur);
-      if (s + 1 < nsteps) store_step(lds + ((s + 1) & 1) * a.buf_u16);
+    auto run = [&](bool mask) {
+      load_step(0);
+      store_step(lds, 0, mask);
       __syncthreads();
-    }
+      for (int s = 0; s < nsteps; ++s) {
+        uint16_t* cur = lds + (s & 1) * a.buf_u16;
+        if (s + 1 < nsteps) load_step(2 * (s + 1));
+        __builtin_amdgcn_sched_barrier(0);   // the next step's loads go out before the MFMAs
+        compute(cur);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s + 1 < nsteps) store_step(lds + ((s + 1) & 1) * a.buf_u16, 2 * (s + 1), mask);
+        __syncthreads();
+      }
+    };
+    if (masked) run(true);
+    else run(false);
   } else {
     for (int s = 0; s < nsteps; ++s) {
       const int cc = 2 * s;
@@ -262,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void mix4_kernel(const MixArgs a) {
       }
       uint16_t* wch = lds + a.woff_u16;
 #pragma unroll
-      for (int k = 0; k < kWItems; ++k) *reinterpret_cast<uint4*>(wch + wlds[k]) = load_w(k, cc);
+      for (int k = 0; k < kWItems; ++k) *reinterpret_cast<uint4*>(wch + wlds[k]) = mask_w(k, cc, load_w(k, cc));
       __syncthreads();
       compute(lds);
       __syncthreads();
