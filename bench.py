@@ -297,13 +297,15 @@ def _counter_rows(d, counter):
 
 
 def _kernel_id(name):
-    """Instance id of a forward kernel name fcfs_fwd_kernel<DT, T, KC, L, LEARNED>."""
+    """Instance id of a forward kernel name fcfs_fwd_kernel<DT, T, KC, L, LEARNED, PAIR>
+    (as fcfs_forward_config reports it)."""
     import re
-    m = re.search(r"fcfs_fwd_kernel<(\d+), (\d+), (\d+), (\d+), (true|false)>", name)
+    m = re.search(r"fcfs_fwd_kernel<(\d+), (\d+), (\d+), (\d+), (true|false)(?:, (true|false))?>", name)
     if not m:
         return None
     dt, t, kc, sl = (int(m.group(i)) for i in range(1, 5))
-    return dt * 1000 + t * 100 + kc * 10 + sl + (10000 if m.group(5) == "true" else 0)
+    return (dt * 1000 + t * 100 + kc * 10 + sl + (10000 if m.group(5) == "true" else 0) +
+            (50000 if m.group(6) == "true" else 0))
 
 
 def write_traffic(fetch_dir, write_dir):
