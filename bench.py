@@ -64,10 +64,17 @@ def case_bytes(fc, plan, shape, esize: int) -> int:
 
 
 def source_hash() -> str:
+    """Hash of the FP32 forward kernel's sources: the kernel, its launch
+    planning and the argument structures it reads (counters taken for other
+    sources are not used)."""
     h = hashlib.sha256()
-    for f in ("fwd_kernel.h", "fwd_f32.hip", "api.cpp", "fcfs_internal.h"):
-        with open(os.path.join(ROOT, "paper_2203_10670_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2203_10670_amd", "csrc")
+    for f in ("fwd_kernel.h", "fwd_f32.hip", "fwd_plan.cpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "fcfs_internal.h"), "rb") as fh:
+        text = fh.read()
+    h.update(text[text.index(b"struct AxisTable"):text.index(b"struct BwdArgs")])
     return h.hexdigest()[:16]
 
 
