@@ -168,7 +168,8 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
  *   LEARNED_MIX4 has no backward in this version (FCFS_E_UNSUPPORTED).
  *   workspace / ws_bytes: device scratch of at least fcfs_backward_workspace
  *        bytes (NULL allowed when that is 0).
- * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small. */
+ * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small,
+ * and FCFS_E_UNSUPPORTED for an output axis of 2^24 samples or more. */
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
                           int64_t w, const void* x, const void* weight, int64_t c_out,
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,

@@ -129,6 +129,19 @@ fcfs_status build_axis(int p, int q, int method, int grid, bool allow_copy, Axis
 // length n with `cells` hidden cells: (most (phase, tap) pairs that read one
 // extended position) x (most extended positions the padding maps onto one
 // input index).
+// Most (phase, tap) pairs that read one extended position.
+static int adjoint_per_position(const AxisTable& t) {
+  int per_pos = 0;
+  for (int r = 0; r < t.q; ++r) {
+    int c = 0;
+    for (int j = 0; j < t.p; ++j)
+      for (int k = 0; k < t.T; ++k)
+        if (mod_pos(t.off[j] + k - r, t.q) == 0) ++c;
+    per_pos = std::max(per_pos, c);
+  }
+  return per_pos;
+}
+
 static int adjoint_cmax(const AxisTable& t, int n, int cells, int pad) {
   int per_pos = 0;
   for (int r = 0; r < t.q; ++r) {
@@ -165,6 +178,7 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
   a->col_blocks = (w + 255) / 256;
   a->cmax_h = adjoint_cmax(plan->ah, h, a->Mh, plan->pad);
   a->cmax_w = adjoint_cmax(plan->aw, w, a->Mw, plan->pad);
+  a->fast_w = adjoint_per_position(plan->aw);
   size_t bytes = align256(sizeof(int) * (size_t)h * (3 + a->cmax_h));
   *off_w = bytes;
   bytes += align256(sizeof(int) * (size_t)w * (3 + a->cmax_w));
@@ -439,6 +453,7 @@ static fcfs_status backward_checks(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n
   if (plan->method == FCFS_LEARNED_MIX4) return FCFS_E_UNSUPPORTED;
   if (plan->method == FCFS_LEARNED_DW4 && plan->ah.p * plan->aw.p > 64) return FCFS_E_UNSUPPORTED;
   if (need_dw && plan->method != FCFS_LEARNED_DW4) return FCFS_E_INVAL;
+  if (*ho >= (1 << 24) || *wo >= (1 << 24)) return FCFS_E_UNSUPPORTED;   // adjoint table entries pack k < 2^24
   return FCFS_OK;
 }
 

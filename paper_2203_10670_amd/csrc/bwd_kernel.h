@@ -8,7 +8,7 @@
 // and for each e every phase j and tap t with q*m + off[j] + t = e. Entries
 // are kept in ascending e, j, t order, so every sum below runs in a fixed
 // order. Table row i: [count, first k, last k, entry 0, entry 1, ...], an
-// entry packing (k << 2) | t.
+// entry packing (k << 7) | (j << 2) | t (output index k = p*m + j < 2^24).
 //
 // Input gradient. One thread per input sample: dx[i][c] = sum over the row
 // entries (kh, th) and column entries (kw, tw) of w * dy[kh][kw], where w is
@@ -22,7 +22,8 @@
 // cells of one (n, c) plane, stages the chunk's dy and padded x in LDS, and
 // has each thread accumulate the 16 taps of one phase over a fixed subset of
 // cells; subsets are then added in a fixed order. The reduce kernel adds the
-// chunks of each channel in a fixed order. Results do not depend on timing.
+// chunks of each (channel, phase, tap) in a fixed order. Results do not
+// depend on timing.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_tables_kernel(const BwdArgs 
         const int m = d / t.q;
         if (m >= cells) continue;
         const int k = t.p * m + j;
-        if (cnt < cmax) row[3 + cnt] = (k << 2) | tap;
+        if (cnt < cmax) row[3 + cnt] = (k << 7) | (j << 2) | tap;
         ++cnt;
         klo = min(klo, k);
         khi = max(khi, k);
@@ -77,42 +78,71 @@ __global__ __launch_bounds__(kThreads) void adjoint_tables_kernel(const BwdArgs 
   row[2] = khi;
 }
 
-template <int DT, bool LEARNED>
+// FE: width entries of a column held in registers (4 or 8, at least the
+// most any interior column has); columns with more (the replicate / reflect
+// edges) take the rest in a loop.
+template <int DT, bool LEARNED, int FE>
 __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
+  constexpr int kFastEntries = FE;
   using S = Store<DT>;
   using TS = typename S::T;
+  extern __shared__ float smem[];   // learned: this channel's taps [p_h][p_w][4][4]
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
   const int64_t per_plane_blocks = (int64_t)a.H * a.col_blocks;
   const int64_t plane = blockIdx.x / per_plane_blocks;
   const int64_t rem = blockIdx.x - plane * per_plane_blocks;
   const int i = (int)(rem / a.col_blocks);
   const int j = (int)(rem % a.col_blocks) * kThreads + threadIdx.x;
+  if constexpr (LEARNED) {
+    const int nwt = TH.p * TW.p * 16;
+    const float* wsrc = a.weight + (int64_t)(plane % a.C) * nwt;
+    for (int k = threadIdx.x; k < nwt; k += kThreads) smem[k] = wsrc[k];
+    __syncthreads();
+  }
   if (plane >= a.planes || j >= a.W) return;
-  const AxisTable& TH = a.th;
-  const AxisTable& TW = a.tw_tab;
   const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
   const int* rw = a.tab_w + (int64_t)j * (3 + a.cmax_w);
   const int nh = rh[0], nw = rw[0];
+  // this column's width entries: output column, and the tap weight (fixed
+  // methods) or the weight's offset within a height phase's block (learned)
+  int kw[kFastEntries];
+  int wo[kFastEntries];
+  float ww[kFastEntries];
+#pragma unroll
+  for (int e = 0; e < kFastEntries; ++e) {
+    const int ent = e < nw ? rw[3 + e] : 0;
+    const int jw = (ent >> 2) & 31, tw = ent & 3;
+    kw[e] = ent >> 7;
+    wo[e] = jw * 16 + tw;
+    ww[e] = LEARNED ? 0.f : TW.w[jw][tw];
+  }
   const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
-  const float* wc = LEARNED ? a.weight + (int64_t)(plane % a.C) * TH.p * TW.p * 16 : nullptr;
   float acc = 0.f;
   for (int eh = 0; eh < nh; ++eh) {
-    const int ph = rh[3 + eh];
-    const int kh = ph >> 2, th = ph & 3;
-    const int jh = kh % TH.p;
+    const int ent = rh[3 + eh];
+    const int kh = ent >> 7, jh = (ent >> 2) & 31, th = ent & 3;
     const TS* dyrow = dyp + (int64_t)kh * a.Wo;
+    float v[kFastEntries];
+#pragma unroll
+    for (int e = 0; e < kFastEntries; ++e) v[e] = S::load(dyrow + kw[e]);   // all issued first
     if constexpr (LEARNED) {
-      const float* wj = wc + (jh * TW.p) * 16 + th * 4;
-      for (int ew = 0; ew < nw; ++ew) {
-        const int pw = rw[3 + ew];
-        const int kw = pw >> 2, tw = pw & 3;
-        acc = __builtin_fmaf(wj[(kw % TW.p) * 16 + tw], S::load(dyrow + kw), acc);
+      const float* wr = smem + jh * TW.p * 16 + th * 4;
+#pragma unroll
+      for (int e = 0; e < kFastEntries; ++e)
+        if (e < nw) acc = __builtin_fmaf(wr[wo[e]], v[e], acc);
+      for (int e = kFastEntries; e < nw; ++e) {
+        const int we = rw[3 + e];
+        acc = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc);
       }
     } else {
       float inner = 0.f;
-      for (int ew = 0; ew < nw; ++ew) {
-        const int pw = rw[3 + ew];
-        const int kw = pw >> 2, tw = pw & 3;
-        inner = __builtin_fmaf(TW.w[kw % TW.p][tw], S::load(dyrow + kw), inner);
+#pragma unroll
+      for (int e = 0; e < kFastEntries; ++e)
+        if (e < nw) inner = __builtin_fmaf(ww[e], v[e], inner);
+      for (int e = kFastEntries; e < nw; ++e) {
+        const int we = rw[3 + e];
+        inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
       }
       acc = __builtin_fmaf(TH.w[jh][th], inner, acc);
     }
@@ -147,15 +177,52 @@ __global__ __launch_bounds__(kThreads) void dw_partial_kernel(const BwdArgs a) {
   float* red = xs + xr * xc;   // [subsets][phases][16]
   const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
   const TS* xp = reinterpret_cast<const TS*>(a.x) + plane * (int64_t)a.H * a.W;
-  for (int idx = threadIdx.x; idx < dyr * dyc; idx += kThreads) {
-    const int rr = idx / dyc, cc = idx % dyc;
-    dys[idx] = S::load(dyp + (int64_t)(TH.p * mh0 + rr) * a.Wo + TW.p * mw0 + cc);
-  }
+  // rows by wave, columns by lane (128-column blocks); loads of four rows
+  // are issued before their stores
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int cb0 = 0; cb0 < dyc; cb0 += 128)
+    for (int rr0 = wave; rr0 < dyr; rr0 += 16) {
+      float v[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rr = min(rr0 + 4 * u, dyr - 1), cc = min(cb0 + lane + 64 * h, dyc - 1);
+          v[u][h] = S::load(dyp + (int64_t)(TH.p * mh0 + rr) * a.Wo + TW.p * mw0 + cc);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (rr0 + 4 * u < dyr && cb0 + lane + 64 * h < dyc) dys[(rr0 + 4 * u) * dyc + cb0 + lane + 64 * h] = v[u][h];
+    }
   const int xr0 = TH.q * mh0 + TH.omin, xc0 = TW.q * mw0 + TW.omin;
-  for (int idx = threadIdx.x; idx < xr * xc; idx += kThreads) {
-    const int rr = idx / xc, cc = idx % xc;
-    const int sr = pad_source(xr0 + rr, a.H, a.pad), sc = pad_source(xc0 + cc, a.W, a.pad);
-    xs[idx] = (sr < 0 || sc < 0) ? 0.f : S::load(xp + (int64_t)sr * a.W + sc);
+  for (int cb0 = 0; cb0 < xc; cb0 += 128) {
+    int scol[2];
+    bool cok[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int sc = pad_source(xc0 + min(cb0 + lane + 64 * h, xc - 1), a.W, a.pad);
+      cok[h] = sc >= 0;
+      scol[h] = sc >= 0 ? sc : 0;
+    }
+    for (int rr0 = wave; rr0 < xr; rr0 += 16) {
+      float v[4][2];
+      bool rok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int sr = pad_source(xr0 + min(rr0 + 4 * u, xr - 1), a.H, a.pad);
+        rok[u] = sr >= 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) v[u][h] = S::load(xp + (int64_t)(sr >= 0 ? sr : 0) * a.W + scol[h]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (rr0 + 4 * u < xr && cb0 + lane + 64 * h < xc)
+            xs[(rr0 + 4 * u) * xc + cb0 + lane + 64 * h] = (rok[u] && cok[h]) ? v[u][h] : 0.f;
+    }
   }
   __syncthreads();
   const int P2 = TH.p * TW.p;
@@ -182,27 +249,39 @@ __global__ __launch_bounds__(kThreads) void dw_partial_kernel(const BwdArgs a) {
     for (int k = 0; k < 16; ++k) rp[k] = acc[k];
   }
   __syncthreads();
-  // add the subsets in a fixed order: thread t handles (phase, tap) pairs
-  float* out = a.partial + ((int64_t)c * a.chunks_per_channel + r) * P2 * 16;
+  // add the subsets in a fixed order: thread t handles (phase, tap) pairs;
+  // partials are laid out [C][phase, tap][chunk]
+  float* out = a.partial + (int64_t)c * P2 * 16 * a.chunks_per_channel + r;
   for (int pt = threadIdx.x; pt < P2 * 16; pt += kThreads) {
     float s = 0.f;
     for (int sb = 0; sb < subsets; ++sb) s += red[sb * P2 * 16 + pt];
-    out[pt] = s;
+    out[(int64_t)pt * a.chunks_per_channel] = s;
   }
 }
 
-// Weight gradient, stage 2: add the chunks of each channel in order.
+// Weight gradient, stage 2: the chunks of each (channel, phase, tap), one
+// wave each: lane l adds chunks l, l + 64, ... in order, then lane 0 adds the
+// 64 lane sums in order.
 template <int DT>
 __global__ __launch_bounds__(kThreads) void dw_reduce_kernel(const BwdArgs a) {
+  extern __shared__ float smem[];
+  float* lsum = smem;   // [kThreads]
   const int P2 = a.th.p * a.tw_tab.p;
-  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (g >= (int64_t)a.C * P2 * 16) return;
-  const int c = (int)(g / (P2 * 16));
-  const int pt = (int)(g % (P2 * 16));
-  const float* src = a.partial + (int64_t)c * a.chunks_per_channel * P2 * 16 + pt;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);   // (c, phase, tap)
+  const bool live = g < (int64_t)a.C * P2 * 16;
   float s = 0.f;
-  for (int r = 0; r < a.chunks_per_channel; ++r) s += src[(int64_t)r * P2 * 16];
-  a.dw[g] = s;   // layout [C][p_h][p_w][4][4] = [C][phase][16]
+  if (live) {
+    const float* src = a.partial + g * a.chunks_per_channel;
+    for (int r = lane; r < a.chunks_per_channel; r += 64) s += src[r];
+  }
+  lsum[threadIdx.x] = s;
+  __syncthreads();
+  if (live && lane == 0) {
+    float t = 0.f;
+    for (int l = 0; l < 64; ++l) t += lsum[threadIdx.x + l];
+    a.dw[g] = t;   // layout [C][p_h][p_w][4][4] = [C][phase][16]
+  }
 }
 
 template <int DT>
@@ -213,16 +292,24 @@ fcfs_status launch_backward_dt(const BwdArgs& a, bool learned, hipStream_t strea
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   if (a.dx) {
     const int64_t blocks = a.planes * (int64_t)a.H * a.col_blocks;
-    if (learned) hipLaunchKernelGGL((dx_kernel<DT, true>), dim3((unsigned)blocks), block, 0, stream, a);
-    else hipLaunchKernelGGL((dx_kernel<DT, false>), dim3((unsigned)blocks), block, 0, stream, a);
+    const size_t wl = sizeof(float) * a.th.p * a.tw_tab.p * 16;
+    const dim3 grid((unsigned)blocks);
+    if (a.fast_w <= 4) {
+      if (learned) hipLaunchKernelGGL((dx_kernel<DT, true, 4>), grid, block, wl, stream, a);
+      else hipLaunchKernelGGL((dx_kernel<DT, false, 4>), grid, block, 0, stream, a);
+    } else {
+      if (learned) hipLaunchKernelGGL((dx_kernel<DT, true, 8>), grid, block, wl, stream, a);
+      else hipLaunchKernelGGL((dx_kernel<DT, false, 8>), grid, block, 0, stream, a);
+    }
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }
   if (a.dw) {
     hipLaunchKernelGGL((dw_partial_kernel<DT>), dim3((unsigned)(a.C * (int64_t)a.chunks_per_channel)), block,
                        a.dw_lds_bytes, stream, a);
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
-    const int64_t n = (int64_t)a.C * a.th.p * a.tw_tab.p * 16;
-    hipLaunchKernelGGL((dw_reduce_kernel<DT>), dim3((unsigned)((n + kThreads - 1) / kThreads)), block, 0, stream, a);
+    const int64_t n = (int64_t)a.C * a.th.p * a.tw_tab.p * 16;   // one wave each
+    hipLaunchKernelGGL((dw_reduce_kernel<DT>), dim3((unsigned)((n + 3) / 4)), block, sizeof(float) * kThreads,
+                       stream, a);
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }
   return FCFS_OK;

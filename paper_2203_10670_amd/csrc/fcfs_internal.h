@@ -89,6 +89,7 @@ struct BwdArgs {
   int pad;
   int col_blocks;        // input-gradient blocks per input row
   int cmax_h, cmax_w;    // adjoint table entries per index
+  int fast_w;            // most width entries of any index away from the padded edges
   int* tab_h;            // adjoint tables (workspace), see bwd_kernel.h
   int* tab_w;
   float* partial;        // weight-gradient partial sums (workspace)
