@@ -329,6 +329,40 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
     const int j0 = g * P, j1 = std::min(plan->aw.p, j0 + P) - 1;
     spread = std::max(spread, plan->aw.off[j1] - plan->aw.off[j0]);
   }
+  // The channel-last kernel: 4 x 32 cells, 16 patch rows (the 4 tap rows of
+  // each cell row), Cc columns of 8-channel pixels plus a spare one, two
+  // stage buffers within the 160 KB of LDS a gfx950 workgroup may use.
+  {
+    const int wspan0 = spread + 4;
+    const int cstep = plan->aw.q < wspan0 ? plan->aw.q : wspan0;
+    const int Cc = cstep * 31 + wspan0;
+    const int CPX = Cc + 2;   // one column of shift to an even start, one spare
+    const int buf_u16 = 16 * CPX * 8 + P * 4 * kMixOut * 4 * 8;
+#ifndef FCFS_MIX_CL_BUFFERS
+#define FCFS_MIX_CL_BUFFERS 1
+#endif
+    const size_t lds = sizeof(uint16_t) * FCFS_MIX_CL_BUFFERS * (size_t)buf_u16;
+    if (Cc + 1 <= 3 * 64 && lds <= 163840 && 2 * c_in * h * w < (int64_t)1 << 31) {
+      a.cl = 1;
+      a.xpair = (w % 2 == 0) && (reinterpret_cast<uintptr_t>(x) & 3) == 0;
+      a.th_cells = 4;
+      a.tw_cells = 32;
+      a.rstep = 4;
+      a.R = 16;
+      a.wspan = wspan0;
+      a.cstep = cstep;
+      a.Cc = Cc;
+      a.CP = CPX;
+      a.buf_u16 = buf_u16;
+      a.nbuf = FCFS_MIX_CL_BUFFERS;
+      a.lds_bytes = (int)lds;
+      a.tiles_h = (a.Mh + 3) / 4;
+      a.tiles_w = (a.Mw + 31) / 32;
+      const int64_t blocks = n * (int64_t)a.tiles_h * a.tiles_w * plan->ah.p * a.groups * a.otiles;
+      if (blocks >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
+      return launch_mix4(dtype, a, stream);
+    }
+  }
   // Cell tile: 128 cells. The first shape whose staged patch travels in
   // registers (at most 8 (channel, row) pairs per wave and 3 column slots of
   // 64) with two stage buffers in 64 KB of LDS (the pipelined kernel); else

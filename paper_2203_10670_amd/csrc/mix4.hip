@@ -1,5 +1,6 @@
 // Instantiation of the channel-mixing MFMA kernels (BF16 and FP16 storage).
 #include "mix4_kernel.h"
+#include "mix4_cl.h"
 
 namespace fcfs {
 

@@ -1,0 +1,376 @@
+// Channel-mixing FCFS layer on MFMA with a channel-last staged patch (gfx950).
+//
+// Same contraction as mix4_kernel.h (per phase (jh, jw): rows = cells,
+// columns = output channels, reduction = (input channel, tap row a, tap
+// column b)), with the reduction ordered so that both MFMA operands are one
+// aligned 16-byte LDS read per lane:
+//   K step (a, 8 input channels): k = 8*b + i  <->  tap column b, channel i.
+// The input patch of a stage (8 input channels) is stored channel-last,
+// [row][pixel][8 channels], so the A fragment of a cell for tap (a, b) is the
+// pixel at (4*lh + a, cstep*lw + b + phase offset): 16 bytes. The weights of
+// the stage are stored [phase][a][output][b][8 channels], so a B fragment is
+// 16 bytes too.
+//
+// Workgroup: 4 waves, 4 x 32 cells (wave w: cell row w, two M tiles of 16
+// cells), kOut = 32 outputs (two N tiles), a group of G width phases, which
+// share the patch. Stages of 8 input channels go through two LDS buffers: the
+// next stage's loads (dword pairs of adjacent columns, or single samples near
+// padded borders) are issued before the stage's MFMAs and stored after them.
+//
+// The patch rows are the 4 tap rows of each of the 4 cell rows (16 rows), the
+// columns a contiguous range (q <= span of a cell's taps) or, for large q, only
+// the tapped columns of each cell.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fcfs_internal.h"
+#include "fwd_kernel.h"
+#include "mix4_kernel.h"
+
+namespace fcfs {
+namespace mix {
+
+constexpr int kClCh = 8;       // input channels per stage
+constexpr int kClRows = 4;     // patch rows per wave (16 = 4 cell rows x 4 tap rows)
+constexpr int kClPairs = 2;    // 128-column slots of column pairs per lane (fast staging)
+constexpr int kClSlots = 3;    // 64-column slots per lane (sample-by-sample staging)
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Fourth word of a raw buffer resource on gfx9-family parts (32-bit data
+// format; reads past the record count return zero).
+constexpr int kBufferWord3 = 0x00020000;
+
+template <int DT, int G, int NBUF>
+__global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(const MixArgs a) {
+  using M = Mfma<DT>;
+  extern __shared__ float smem[];
+  uint16_t* const lds = reinterpret_cast<uint16_t*>(smem);
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+
+  int64_t blk = blockIdx.x;
+  const int otile = (int)(blk % a.otiles); blk /= a.otiles;
+  const int group = (int)(blk % a.groups); blk /= a.groups;
+  const int jh = (int)(blk % TH.p); blk /= TH.p;
+  const int tcol = (int)(blk % a.tiles_w); blk /= a.tiles_w;
+  const int trow = (int)(blk % a.tiles_h); blk /= a.tiles_h;
+  const int n = (int)blk;
+
+  const int mh0 = trow * 4, mw0 = tcol * 32;
+  const int jw0 = group * G;
+  const int P = min(G, TW.p - jw0);
+  const int o0 = otile * kOut;
+  const int r0 = TH.q * mh0 + TH.off[jh];
+  const int cbase = TW.off[jw0];
+  const int c0 = TW.q * mw0 + cbase;
+  const bool contiguous = a.cstep == TW.q;
+  const int cs = contiguous ? (c0 & ~1) : c0;   // input column of patch pixel 0 (even when contiguous)
+  const int sh = c0 - cs;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g4 = lane >> 4;
+  const int li = lane & 15;
+  const int CPX = a.CP;                          // pixels per patch row
+  const int patch_u16 = 16 * CPX * kClCh;        // weights follow
+  const int64_t plane = (int64_t)a.H * a.W;
+  const uint16_t* xin = reinterpret_cast<const uint16_t*>(a.x) + (int64_t)n * a.Cin * plane;
+  const uint16_t* win = reinterpret_cast<const uint16_t*>(a.w);
+
+  auto src_row = [&](int rr) -> int { return fwd::pad_source(r0 + TH.q * (rr >> 2) + (rr & 3), a.H, a.pad); };
+  auto src_col = [&](int px) -> int {   // input column of patch pixel px (before padding)
+    return contiguous ? cs + px : c0 + TW.q * (px / a.wspan) + px % a.wspan;
+  };
+
+  // Pair staging applies when the patch columns are contiguous and rows hold
+  // whole aligned pairs; pixels whose column lies outside the row are then
+  // fixed up from the patch itself.
+  const int npx = a.Cc + sh;   // pixels the MFMAs read
+  const bool pairs = contiguous && a.xpair;
+  const int pad_left = pairs ? max(0, -cs) : 0;
+  const int pad_right = pairs ? max(0, cs + npx - a.W) : 0;
+
+  // ---- weights: items it = tid + 256 k: (phase, output, channel pair) =
+  // (it / 128, (it / 4) % 32, it % 4); each moves 2 channels x 16 taps
+  constexpr int kWItems = (G * kOut * 4 + kThreads - 1) / kThreads;
+  int64_t woff[kWItems];
+  int wlds[kWItems];
+  bool wok[kWItems];     // the quad's phase and output exist (zeros otherwise)
+  bool wlive[kWItems];   // the item exists (it < G * 128)
+  int wch[kWItems];
+#pragma unroll
+  for (int k = 0; k < kWItems; ++k) {
+    const int it = tid + kThreads * k;
+    const int ph = it / (kOut * 4), o = (it >> 2) % kOut, cq = it & 3;
+    wlive[k] = it < G * kOut * 4;
+    wok[k] = wlive[k] && ph < P && o0 + o < a.Cout;
+    wch[k] = 2 * cq;
+    woff[k] = wok[k] ? ((((int64_t)jh * TW.p + jw0 + ph) * a.Cout + o0 + o) * a.Cin + 2 * cq) * 16 : 0;
+    // u16 offset of (ph, a = 0, o, b = 0, channels 2cq, 2cq+1); a adds kOut*4*8, b adds 8
+    wlds[k] = patch_u16 + ((ph * 4 * kOut + o) * 4) * kClCh + 2 * cq;
+  }
+  uint4 wpre[NBUF == 1 ? 1 : kWItems][4];
+  auto load_w = [&](int cb) {
+    if constexpr (NBUF == 1) return;   // (staged item by item in store_w)
+#pragma unroll
+    for (int k = 0; k < kWItems; ++k) {
+      // each of the two channels only when it exists (the second may be past C_in)
+      const bool ok0 = wok[k] && cb + wch[k] < a.Cin, ok1 = wok[k] && cb + wch[k] + 1 < a.Cin;
+      const uint16_t* src0 = win + (ok0 ? woff[k] + (int64_t)cb * 16 : 0);
+      const uint16_t* src1 = win + (ok1 ? woff[k] + (int64_t)cb * 16 + 16 : 0);
+      wpre[k][0] = *reinterpret_cast<const uint4*>(src0);
+      wpre[k][1] = *reinterpret_cast<const uint4*>(src0 + 8);
+      wpre[k][2] = *reinterpret_cast<const uint4*>(src1);
+      wpre[k][3] = *reinterpret_cast<const uint4*>(src1 + 8);
+    }
+  };
+  auto store_w = [&](uint16_t* buf, int cb) {
+#pragma unroll
+    for (int k = 0; k < kWItems; ++k) {
+      if (!wlive[k]) continue;
+      if constexpr (NBUF == 1) {   // loaded here, one item at a time (few registers)
+        const bool ok0 = wok[k] && cb + wch[k] < a.Cin, ok1 = wok[k] && cb + wch[k] + 1 < a.Cin;
+        const uint16_t* src0 = win + (ok0 ? woff[k] + (int64_t)cb * 16 : 0);
+        const uint16_t* src1 = win + (ok1 ? woff[k] + (int64_t)cb * 16 + 16 : 0);
+        wpre[0][0] = *reinterpret_cast<const uint4*>(src0);
+        wpre[0][1] = *reinterpret_cast<const uint4*>(src0 + 8);
+        wpre[0][2] = *reinterpret_cast<const uint4*>(src1);
+        wpre[0][3] = *reinterpret_cast<const uint4*>(src1 + 8);
+      }
+      const int kk = NBUF == 1 ? 0 : k;
+      const uint32_t m0 = (wok[k] && cb + wch[k] < a.Cin) ? 0xffffu : 0u;
+      const uint32_t m1 = (wok[k] && cb + wch[k] + 1 < a.Cin) ? 0xffffu : 0u;
+      const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&wpre[kk][0]);   // channel 2cq: 16 taps
+      const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&wpre[kk][2]);   // channel 2cq + 1
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const uint32_t lo = (w0[t >> 1] >> (16 * (t & 1))) & m0;
+        const uint32_t hi = (w1[t >> 1] >> (16 * (t & 1))) & m1;
+        const int ta = t >> 2, tb = t & 3;
+        *reinterpret_cast<uint32_t*>(buf + wlds[k] + (ta * kOut * 4 + tb) * kClCh) = lo | (hi << 16);
+      }
+    }
+  };
+
+  // ---- patch, pair staging: rows rr = wave + 4 i, column pairs
+  // cs + 2 lane + 128 j (+1), 8 channels
+  uint32_t poff[kClRows][kClPairs];   // byte offset of the pair in a channel plane
+#pragma unroll
+  for (int i = 0; i < kClRows; ++i) {
+    const int sr = src_row(wave + 4 * i);
+#pragma unroll
+    for (int j = 0; j < kClPairs; ++j) {
+      const int c = min(max(cs + 2 * lane + 128 * j, 0), a.W - 2);   // clamped into the row
+      // a zero-padding row takes a lane offset past the buffer's range, for
+      // which the load returns zero
+      poff[i][j] = sr >= 0 ? 2u * (uint32_t)(sr * a.W + c) : 0x7ffffffcu;
+    }
+  }
+  // LDS pixel of each of the lane's two pixels per slot: pixels past the
+  // patch, and pixels of columns outside the row (whose loads were clamped),
+  // go to the spare pixel
+  int pdst[kClPairs][2];
+#pragma unroll
+  for (int j = 0; j < kClPairs; ++j)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int px = 2 * lane + 128 * j + e;
+      pdst[j][e] = (px < npx && cs + px >= 0 && cs + px < a.W) ? px : CPX - 1;
+    }
+  uint32_t pre[kClRows][kClPairs][kClCh];
+  // The image's input as a raw buffer (the host keeps it under 2^31 bytes):
+  // each load is the lane's offset in a plane plus the channel's offset as a
+  // scalar, with no per-load address arithmetic.
+  const __amdgpu_buffer_rsrc_t xrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)xin, 0, (int)(2 * plane * a.Cin), kBufferWord3);
+  auto load_patch = [&](int cb) {
+#pragma unroll
+    for (int ch = 0; ch < kClCh; ++ch) {
+      // the scalar offset stays inside the tensor: the range check of a raw
+      // buffer covers the lane offset, not necessarily the scalar one
+      const int soff = 2 * (int)plane * min(cb + ch, a.Cin - 1);
+#pragma unroll
+      for (int i = 0; i < kClRows; ++i)
+#pragma unroll
+        for (int j = 0; j < kClPairs; ++j)
+          pre[i][j][ch] = __builtin_amdgcn_raw_buffer_load_b32(xrs, (int)poff[i][j], soff, 0);
+    }
+  };
+  auto store_patch = [&](uint16_t* buf, int cb) {
+#pragma unroll
+    for (int i = 0; i < kClRows; ++i) {
+#pragma unroll
+      for (int j = 0; j < kClPairs; ++j) {
+        uint32_t v[kClCh];   // zero-padding rows came back as zeros; channels past C_in are zeroed here
+#pragma unroll
+        for (int ch = 0; ch < kClCh; ++ch) v[ch] = cb + ch < a.Cin ? pre[i][j][ch] : 0u;
+        u32x4 p0, p1;   // pixel 2 lane + 128 j (low halves) and the next (high halves)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          p0[h] = (v[2 * h] & 0xffffu) | (v[2 * h + 1] << 16);
+          p1[h] = (v[2 * h] >> 16) | (v[2 * h + 1] & 0xffff0000u);
+        }
+        const int rr = wave + 4 * i;
+        *reinterpret_cast<u32x4*>(buf + (rr * CPX + pdst[j][0]) * kClCh) = p0;
+        *reinterpret_cast<u32x4*>(buf + (rr * CPX + pdst[j][1]) * kClCh) = p1;
+      }
+    }
+  };
+  // pixels of columns outside the row (pair staging near a border): the
+  // samples the padding maps them to, fetched one by one, or zero
+  auto fix_pad = [&](uint16_t* buf, int cb) {
+    const int npad = pad_left + pad_right;
+    for (int it = tid; it < 16 * npad; it += kThreads) {
+      const int rr = it / npad, s = it - rr * npad;
+      const int px = s < pad_left ? s : a.W - cs + (s - pad_left);
+      const int sr = src_row(rr);
+      const int sc = fwd::pad_source(cs + px, a.W, a.pad);
+      uint32_t v[kClCh];
+#pragma unroll
+      for (int ch = 0; ch < kClCh; ++ch)
+        v[ch] = (sr >= 0 && sc >= 0 && cb + ch < a.Cin) ? xin[(cb + ch) * plane + (int64_t)sr * a.W + sc] : 0u;
+      u32x4 p;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) p[h] = v[2 * h] | (v[2 * h + 1] << 16);
+      *reinterpret_cast<u32x4*>(buf + (rr * CPX + px) * kClCh) = p;
+    }
+  };
+  // sample-by-sample staging (large q, or rows without aligned pairs)
+  auto stage_samples = [&](uint16_t* buf, int cb) {
+    for (int i = 0; i < kClRows; ++i) {
+      const int rr = wave + 4 * i;
+      const int sr = src_row(rr);
+      for (int j = 0; j < kClSlots; ++j) {
+        const int px = lane + 64 * j;
+        if (px >= npx) continue;
+        const int sc = fwd::pad_source(src_col(px), a.W, a.pad);
+        uint32_t v[kClCh];
+#pragma unroll
+        for (int ch = 0; ch < kClCh; ++ch)
+          v[ch] = (sr >= 0 && sc >= 0 && cb + ch < a.Cin) ? xin[(cb + ch) * plane + (int64_t)sr * a.W + sc] : 0u;
+        u32x4 p;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) p[h] = v[2 * h] | (v[2 * h + 1] << 16);
+        *reinterpret_cast<u32x4*>(buf + (rr * CPX + px) * kClCh) = p;
+      }
+    }
+  };
+
+  // ---- fragments
+  int apx[2];   // pixel of this lane's cell for tap column b = g4 (phase offset added per phase)
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) apx[mt] = (4 * wave) * CPX + a.cstep * (mt * 16 + li) + sh + g4;
+  constexpr int kNT = kOut / 16;
+  f32x4 acc[G][2][kNT];
+#pragma unroll
+  for (int ph = 0; ph < G; ++ph)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](const uint16_t* buf) {
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+      for (int ph = 0; ph < G; ++ph) {
+        const int dcol = ph < P ? TW.off[jw0 + ph] - cbase : 0;
+        u16x8 af[2], bf[kNT];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+          af[mt] = *reinterpret_cast<const u16x8*>(buf + (apx[mt] + ta * CPX + dcol) * kClCh);
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt)
+          bf[nt] = *reinterpret_cast<const u16x8*>(buf + patch_u16 +
+                                                   (((ph * 4 + ta) * kOut + nt * 16 + li) * 4 + g4) * kClCh);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = M::mma(af[mt], bf[nt], acc[ph][mt][nt]);
+      }
+  };
+
+  const int nst = (a.Cin + kClCh - 1) / kClCh;
+  uint16_t* const buf0 = lds;
+  uint16_t* const buf1 = lds + a.buf_u16;
+  if (pairs) {
+    const bool fix = pad_left + pad_right > 0;
+    load_patch(0);
+    load_w(0);
+    store_patch(buf0, 0);
+    store_w(buf0, 0);
+    if (fix) fix_pad(buf0, 0);   // disjoint pixels: no barrier between
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+      // two buffers: the next stage lands in the other one; one buffer: it
+      // lands after every wave is done with this stage (another workgroup on
+      // the compute unit keeps the matrix cores busy meanwhile)
+      uint16_t* cur = (NBUF == 2 && (s & 1)) ? buf1 : buf0;
+      uint16_t* nxt = NBUF == 2 ? ((s & 1) ? buf0 : buf1) : buf0;
+      if (s + 1 < nst) {
+        load_patch(kClCh * (s + 1));
+        load_w(kClCh * (s + 1));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      compute(cur);
+      __builtin_amdgcn_sched_barrier(0);
+      if (s + 1 < nst) {
+        if (NBUF == 1) __syncthreads();
+        store_patch(nxt, kClCh * (s + 1));
+        store_w(nxt, kClCh * (s + 1));
+        if (fix) fix_pad(nxt, kClCh * (s + 1));
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int s = 0; s < nst; ++s) {
+      stage_samples(buf0, kClCh * s);
+      load_w(kClCh * s);
+      store_w(buf0, kClCh * s);
+      __syncthreads();
+      compute(buf0);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: 16 output channels at a time through LDS, whole row segments out
+  uint16_t* ob = lds;   // [16][4][32 * P]
+  const int segw = 32 * P;
+  uint16_t* yout = reinterpret_cast<uint16_t*>(a.y);
+#pragma unroll
+  for (int nt = 0; nt < kNT; ++nt) {
+#pragma unroll
+    for (int ph = 0; ph < G; ++ph) {
+      if (ph >= P) break;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int lw = mt * 16 + 4 * g4 + i;   // cell row = wave
+          ob[(li * 4 + wave) * segw + lw * P + ph] = M::to_store(acc[ph][mt][nt][i]);
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 16 * 4 * segw; idx += kThreads) {
+      const int row = idx / segw, e = idx - row * segw;
+      const int ol = row >> 2, lh = row & 3;
+      const int lw = e / P, ph = e - lw * P;
+      const int o = o0 + nt * 16 + ol, mh = mh0 + lh, mw = mw0 + lw;
+      if (o < a.Cout && mh < a.Mh && mw < a.Mw)
+        __builtin_nontemporal_store(ob[idx], yout + (((int64_t)n * a.Cout + o) * a.Ho + TH.p * mh + jh) * a.Wo +
+                                                 TW.p * mw + jw0 + ph);
+    }
+    __syncthreads();
+  }
+}
+
+template <int DT, int G>
+void launch_cl(const MixArgs& a, dim3 grid, hipStream_t stream) {
+  if (a.nbuf == 2) hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 2>), grid, dim3(kThreads), a.lds_bytes, stream, a);
+  else hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 1>), grid, dim3(kThreads), a.lds_bytes, stream, a);
+}
+
+}  // namespace mix
+}  // namespace fcfs

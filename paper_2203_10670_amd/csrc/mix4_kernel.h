@@ -332,10 +332,23 @@ void launch_g(const MixArgs& a, dim3 grid, hipStream_t stream) {
   else hipLaunchKernelGGL((mix4_kernel<DT, G, false>), grid, dim3(kThreads), a.lds_bytes, stream, a);
 }
 
+template <int DT, int G>
+void launch_cl(const MixArgs& a, dim3 grid, hipStream_t stream);
+
 template <int DT>
 fcfs_status launch_mix4_dt(const MixArgs& a, hipStream_t stream) {
   const int64_t blocks = (int64_t)a.N * a.tiles_h * a.tiles_w * a.th.p * a.groups * a.otiles;
   const dim3 grid((unsigned)blocks);
+  if (a.cl) {
+    switch (a.gsize) {
+      case 1: launch_cl<DT, 1>(a, grid, stream); break;
+      case 2: launch_cl<DT, 2>(a, grid, stream); break;
+      case 3: launch_cl<DT, 3>(a, grid, stream); break;
+      case 4: launch_cl<DT, 4>(a, grid, stream); break;
+      default: launch_cl<DT, 5>(a, grid, stream); break;
+    }
+    return hipGetLastError() == hipSuccess ? FCFS_OK : FCFS_E_DEVICE;
+  }
   switch (a.gsize) {
     case 1: launch_g<DT, 1>(a, grid, stream); break;
     case 2: launch_g<DT, 2>(a, grid, stream); break;

@@ -7,6 +7,8 @@
 #include <barrier>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -57,6 +59,32 @@ inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); r
 #define __syncthreads() (hostemu::block_bar_->arrive_and_wait())
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 #define __builtin_nontemporal_load(p) (*(p))
+
+// Raw buffer resources: base and record count; reads past the count return 0.
+namespace hostemu {
+struct BufferRsrc {
+  const char* base;
+  int64_t records;
+};
+inline BufferRsrc make_buffer_rsrc(void* p, int, int num, int) { return BufferRsrc{static_cast<const char*>(p), num}; }
+// Out-of-range loads return zero. Only the lane offset is trusted to be range
+// checked: a load whose lane offset is in range but whose sum with the scalar
+// offset is not would read outside the buffer on the device, so it aborts here.
+inline uint32_t raw_buffer_load_b32(BufferRsrc r, int voff, int soff, int) {
+  if (voff < 0 || (int64_t)voff + 4 > r.records) return 0u;
+  const int64_t off = (int64_t)voff + soff;
+  if (soff < 0 || off + 4 > r.records) {
+    std::fprintf(stderr, "raw buffer load past the range: voff %d soff %d records %d\n", voff, soff, r.records);
+    std::abort();
+  }
+  uint32_t v;
+  std::memcpy(&v, r.base + off, 4);
+  return v;
+}
+}  // namespace hostemu
+typedef hostemu::BufferRsrc __amdgpu_buffer_rsrc_t;
+#define __builtin_amdgcn_make_buffer_rsrc(p, stride, num, flags) hostemu::make_buffer_rsrc(p, stride, num, flags)
+#define __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux) hostemu::raw_buffer_load_b32(r, voff, soff, aux)
 
 struct uint4 {
   unsigned x, y, z, w;

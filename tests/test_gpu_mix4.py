@@ -40,7 +40,8 @@ def check(y, x, w, p, q, pad, dtype, cout, what):
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 @pytest.mark.parametrize("p,q,pad", [(5, 4, "reflect"), (3, 2, "zero"), (2, 3, "replicate"), (7, 5, "reflect"),
-                                     (3, 4, "zero"), (1, 1, "zero"), (2, 7, "reflect"), (9, 8, "replicate")])
+                                     (3, 4, "zero"), (1, 1, "zero"), (2, 7, "reflect"), (9, 8, "replicate"),
+                                     (6, 5, "reflect")])
 def test_mix4_small(dtype, p, q, pad):
     from math import gcd
     g = gcd(p, q)

@@ -126,6 +126,9 @@ def test_channel_mixing_mfma():
                   "cout": 3})
     cases.append({"p": 9, "q": 8, "method": "mix4", "pad": "replicate", "dtype": "f16", "shape": [1, 3, 20, 75],
                   "cout": 4})
+    # a second width-phase group that starts at an odd column (and has one phase)
+    cases.append({"p": 6, "q": 5, "method": "mix4", "pad": "reflect", "dtype": "bf16", "shape": [1, 9, 12, 170],
+                  "cout": 3})
     cases.append({"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 2, 8, 8],
                   "cout": 2, "expect_status": 2})
     _run(cases)
