@@ -131,26 +131,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wave order: FCFS_FWD_BAND_FASTEST = 1 makes consecutive waves (and so the
-// four waves of a workgroup) take consecutive bands of one strip, whose
-// overlapping halo rows then meet in the same cache; 0 takes the strips of
-// one band first.
-#ifndef FCFS_FWD_BAND_FASTEST
-#define FCFS_FWD_BAND_FASTEST 0
-#endif
-__device__ __forceinline__ int wave_strip(const FwdArgs& a, int64_t wid) {
-  return FCFS_FWD_BAND_FASTEST ? (int)((wid / a.bands) % a.strips) : (int)(wid % a.strips);
-}
-__device__ __forceinline__ int wave_band(const FwdArgs& a, int64_t wid) {
-  return FCFS_FWD_BAND_FASTEST ? (int)(wid % a.bands) : (int)((wid / a.strips) % a.bands);
-}
-
 // Input column the strip of wave `wid` stages first, aligned down to an even
 // column in paired mode.
 template <bool PAIR>
 __device__ __forceinline__ int strip_first_column(const FwdArgs& a, int64_t wid) {
   const AxisTable& TW = a.tw_tab;
-  const int ow0 = wave_strip(a, wid) * a.tw;
+  const int ow0 = (int)(wid % a.strips) * a.tw;
   const int c = TW.q * (ow0 / TW.p) + TW.omin;
   return PAIR ? (c & ~1) : c;
 }
@@ -169,9 +155,10 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
 
-  const int strip = wave_strip(a, wid);
-  const int band = wave_band(a, wid);
-  const int64_t plane = wid / ((int64_t)a.strips * a.bands);
+  const int strip = (int)(wid % a.strips);
+  const int64_t t1 = wid / a.strips;
+  const int band = (int)(t1 % a.bands);
+  const int64_t plane = t1 / a.bands;
 
   const int ow0 = strip * a.tw;
   const int owEnd = min(ow0 + a.tw, a.Wo);
