@@ -330,13 +330,18 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
     spread = std::max(spread, plan->aw.off[j1] - plan->aw.off[j0]);
   }
   // The channel-last kernel: 4 x 32 cells, 16 patch rows (the 4 tap rows of
-  // each cell row), Cc columns of 8-channel pixels plus a spare one, two
-  // stage buffers within the 160 KB of LDS a gfx950 workgroup may use.
+  // each cell row), Cc columns of 8-channel pixels (plus one of shift to an
+  // even start) held in cstep residue classes of S slots, a spare slot, and
+  // a row pitch of 16 mod 32 slots (the half-wave reading two rows then
+  // covers all 128 LDS banks once), within the 160 KB of LDS a gfx950
+  // workgroup may use.
   {
     const int wspan0 = spread + 4;
     const int cstep = plan->aw.q < wspan0 ? plan->aw.q : wspan0;
     const int Cc = cstep * 31 + wspan0;
-    const int CPX = Cc + 2;   // one column of shift to an even start, one spare
+    const int S = (Cc + 1 + cstep - 1) / cstep;
+    int CPX = cstep * S + 1;
+    CPX += ((16 - CPX) % 32 + 32) % 32;
     const int buf_u16 = 16 * CPX * 8 + P * 4 * kMixOut * 4 * 8;
 #ifndef FCFS_MIX_CL_BUFFERS
 #define FCFS_MIX_CL_BUFFERS 1
@@ -353,6 +358,7 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
       a.cstep = cstep;
       a.Cc = Cc;
       a.CP = CPX;
+      a.slots = S;
       a.buf_u16 = buf_u16;
       a.nbuf = FCFS_MIX_CL_BUFFERS;
       a.lds_bytes = (int)lds;

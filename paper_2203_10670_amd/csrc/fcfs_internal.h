@@ -120,7 +120,8 @@ struct MixArgs {
   int wspan;                 // columns a cell's taps cover over the phase group
   int npr, ncs, items;       // (channel, row) pairs per wave, 64-column slots per row, items per lane
   int nbuf;                  // LDS stage buffers (2, or 1 when two do not fit)
-  int cl;                    // 1: the channel-last kernel (CP counts pixels of 8 channels)
+  int cl;                    // 1: the channel-last kernel (CP counts 16-byte slots of 8 channels)
+  int slots;                 // channel-last: slots per residue class of a patch row
   int xpair;                 // x rows hold aligned pairs of samples (even W, 4-byte aligned x)
   int buf_u16, woff_u16;     // LDS stage buffer size and weight offset in it (16-bit units):
                              // patch [2][R][CP], then weights [gsize][32][32] and a spare quad

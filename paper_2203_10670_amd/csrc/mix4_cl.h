@@ -73,7 +73,9 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g4 = lane >> 4;
   const int li = lane & 15;
-  const int CPX = a.CP;                          // pixels per patch row
+  const int CPX = a.CP;                          // 16-byte slots per patch row (16 mod 32)
+  const int S = a.slots;                         // slots per residue class of a row
+  const int cstep = a.cstep;
   const int patch_u16 = 16 * CPX * kClCh;        // weights follow
   const int64_t plane = (int64_t)a.H * a.W;
   const uint16_t* xin = reinterpret_cast<const uint16_t*>(a.x) + (int64_t)n * a.Cin * plane;
@@ -83,6 +85,10 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
   auto src_col = [&](int px) -> int {   // input column of patch pixel px (before padding)
     return contiguous ? cs + px : c0 + TW.q * (px / a.wspan) + px % a.wspan;
   };
+  // Slot of patch pixel px in its row: pixels are grouped by px mod cstep, so
+  // that the pixels one tap column of 16 consecutive cells reads are 16
+  // consecutive slots.
+  auto slot_of = [&](int px) -> int { return (px % cstep) * S + px / cstep; };
 
   // Pair staging applies when the patch columns are contiguous and rows hold
   // whole aligned pairs; pixels whose column lies outside the row are then
@@ -92,6 +98,7 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
   const int pad_left = pairs ? max(0, -cs) : 0;
   const int pad_right = pairs ? max(0, cs + npx - a.W) : 0;
 
+  constexpr int kNT = kOut / 16;
   // ---- weights: items it = tid + 256 k: (phase, output, channel pair) =
   // (it / 128, (it / 4) % 32, it % 4); each moves 2 channels x 16 taps
   constexpr int kWItems = (G * kOut * 4 + kThreads - 1) / kThreads;
@@ -108,8 +115,10 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
     wok[k] = wlive[k] && ph < P && o0 + o < a.Cout;
     wch[k] = 2 * cq;
     woff[k] = wok[k] ? ((((int64_t)jh * TW.p + jw0 + ph) * a.Cout + o0 + o) * a.Cin + 2 * cq) * 16 : 0;
-    // u16 offset of (ph, a = 0, o, b = 0, channels 2cq, 2cq+1); a adds kOut*4*8, b adds 8
-    wlds[k] = patch_u16 + ((ph * 4 * kOut + o) * 4) * kClCh + 2 * cq;
+    // u16 offset of (ph, b = 0, o, a = 0, channels 2cq, 2cq+1) in the layout
+    // [phase][b][N tile][a][output in the tile][8 channels]: a B fragment is
+    // then 64 consecutive 16-byte chunks, one per lane
+    wlds[k] = patch_u16 + (((ph * 4 * kNT + o / 16) * 4) * 16 + o % 16) * kClCh + 2 * cq;
   }
   uint4 wpre[NBUF == 1 ? 1 : kWItems][4];
   auto load_w = [&](int cb) {
@@ -126,12 +135,17 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
       wpre[k][3] = *reinterpret_cast<const uint4*>(src1 + 8);
     }
   };
+  // Two channels' 16 taps (words of two taps each) become 16 words of one tap
+  // and the two channels; only the last stage can hold channels past C_in,
+  // which it zeroes (a missing output or phase only feeds results that are
+  // never stored).
   auto store_w = [&](uint16_t* buf, int cb) {
+    const bool tail = cb + kClCh > a.Cin;
 #pragma unroll
     for (int k = 0; k < kWItems; ++k) {
       if (!wlive[k]) continue;
+      const bool ok0 = wok[k] && cb + wch[k] < a.Cin, ok1 = wok[k] && cb + wch[k] + 1 < a.Cin;
       if constexpr (NBUF == 1) {   // loaded here, one item at a time (few registers)
-        const bool ok0 = wok[k] && cb + wch[k] < a.Cin, ok1 = wok[k] && cb + wch[k] + 1 < a.Cin;
         const uint16_t* src0 = win + (ok0 ? woff[k] + (int64_t)cb * 16 : 0);
         const uint16_t* src1 = win + (ok1 ? woff[k] + (int64_t)cb * 16 + 16 : 0);
         wpre[0][0] = *reinterpret_cast<const uint4*>(src0);
@@ -140,16 +154,21 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
         wpre[0][3] = *reinterpret_cast<const uint4*>(src1 + 8);
       }
       const int kk = NBUF == 1 ? 0 : k;
-      const uint32_t m0 = (wok[k] && cb + wch[k] < a.Cin) ? 0xffffu : 0u;
-      const uint32_t m1 = (wok[k] && cb + wch[k] + 1 < a.Cin) ? 0xffffu : 0u;
-      const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&wpre[kk][0]);   // channel 2cq: 16 taps
-      const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&wpre[kk][2]);   // channel 2cq + 1
+      uint32_t w0[8], w1[8];   // channel 2cq and 2cq + 1: 16 taps each
+      __builtin_memcpy(w0, &wpre[kk][0], 32);
+      __builtin_memcpy(w1, &wpre[kk][2], 32);
+      if (tail) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          w0[t] = ok0 ? w0[t] : 0u;
+          w1[t] = ok1 ? w1[t] : 0u;
+        }
+      }
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        const uint32_t lo = (w0[t >> 1] >> (16 * (t & 1))) & m0;
-        const uint32_t hi = (w1[t >> 1] >> (16 * (t & 1))) & m1;
         const int ta = t >> 2, tb = t & 3;
-        *reinterpret_cast<uint32_t*>(buf + wlds[k] + (ta * kOut * 4 + tb) * kClCh) = lo | (hi << 16);
+        const uint32_t v = __builtin_amdgcn_perm(w1[t >> 1], w0[t >> 1], (t & 1) ? 0x07060302u : 0x05040100u);
+        *reinterpret_cast<uint32_t*>(buf + wlds[k] + (tb * kNT * 64 + ta * 16) * kClCh) = v;
       }
     }
   };
@@ -177,7 +196,7 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int px = 2 * lane + 128 * j + e;
-      pdst[j][e] = (px < npx && cs + px >= 0 && cs + px < a.W) ? px : CPX - 1;
+      pdst[j][e] = (px < npx && cs + px >= 0 && cs + px < a.W) ? slot_of(px) : CPX - 1;
     }
   uint32_t pre[kClRows][kClPairs][kClCh];
   // The image's input as a raw buffer (the host keeps it under 2^31 bytes):
@@ -199,18 +218,27 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
     }
   };
   auto store_patch = [&](uint16_t* buf, int cb) {
+    // zero-padding rows came back as zeros; channels past C_in (last stage
+    // only) are zeroed here
+    if (cb + kClCh > a.Cin) {
+#pragma unroll
+      for (int ch = 0; ch < kClCh; ++ch)
+        if (cb + ch >= a.Cin)
+#pragma unroll
+          for (int i = 0; i < kClRows; ++i)
+#pragma unroll
+            for (int j = 0; j < kClPairs; ++j) pre[i][j][ch] = 0u;
+    }
 #pragma unroll
     for (int i = 0; i < kClRows; ++i) {
 #pragma unroll
       for (int j = 0; j < kClPairs; ++j) {
-        uint32_t v[kClCh];   // zero-padding rows came back as zeros; channels past C_in are zeroed here
-#pragma unroll
-        for (int ch = 0; ch < kClCh; ++ch) v[ch] = cb + ch < a.Cin ? pre[i][j][ch] : 0u;
+        const uint32_t* v = pre[i][j];
         u32x4 p0, p1;   // pixel 2 lane + 128 j (low halves) and the next (high halves)
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-          p0[h] = (v[2 * h] & 0xffffu) | (v[2 * h + 1] << 16);
-          p1[h] = (v[2 * h] >> 16) | (v[2 * h + 1] & 0xffff0000u);
+          p0[h] = __builtin_amdgcn_perm(v[2 * h + 1], v[2 * h], 0x05040100u);
+          p1[h] = __builtin_amdgcn_perm(v[2 * h + 1], v[2 * h], 0x07060302u);
         }
         const int rr = wave + 4 * i;
         *reinterpret_cast<u32x4*>(buf + (rr * CPX + pdst[j][0]) * kClCh) = p0;
@@ -234,7 +262,7 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
       u32x4 p;
 #pragma unroll
       for (int h = 0; h < 4; ++h) p[h] = v[2 * h] | (v[2 * h + 1] << 16);
-      *reinterpret_cast<u32x4*>(buf + (rr * CPX + px) * kClCh) = p;
+      *reinterpret_cast<u32x4*>(buf + (rr * CPX + slot_of(px)) * kClCh) = p;
     }
   };
   // sample-by-sample staging (large q, or rows without aligned pairs)
@@ -253,16 +281,21 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
         u32x4 p;
 #pragma unroll
         for (int h = 0; h < 4; ++h) p[h] = v[2 * h] | (v[2 * h + 1] << 16);
-        *reinterpret_cast<u32x4*>(buf + (rr * CPX + px) * kClCh) = p;
+        *reinterpret_cast<u32x4*>(buf + (rr * CPX + slot_of(px)) * kClCh) = p;
       }
     }
   };
 
-  // ---- fragments
-  int apx[2];   // pixel of this lane's cell for tap column b = g4 (phase offset added per phase)
+  // ---- fragments. K step (tap column b, 8 input channels): k = 8 a + i
+  // <-> tap row a, channel i. Lane (li, g4) of an A fragment reads patch row
+  // 4 wave + g4 at the cell's pixel for column offset d = dcol(phase) + b,
+  // which depends on the phase only through d: one A fragment per d serves
+  // every (phase, b) with that d. B fragments are 64 consecutive chunks.
+  const int abase = ((4 * wave + g4) * CPX + li) * kClCh;
+  int dcol[G];   // tap column offset of each phase in the group (none past P)
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) apx[mt] = (4 * wave) * CPX + a.cstep * (mt * 16 + li) + sh + g4;
-  constexpr int kNT = kOut / 16;
+  for (int ph = 0; ph < G; ++ph) dcol[ph] = ph < P ? TW.off[jw0 + ph] - cbase : -64;
+  const int res0 = sh % cstep, quo0 = sh / cstep;   // class and index of pixel sh + 0 of cell 0
   f32x4 acc[G][2][kNT];
 #pragma unroll
   for (int ph = 0; ph < G; ++ph)
@@ -272,24 +305,38 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
       for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   auto compute = [&](const uint16_t* buf) {
+    int res = res0, quo = quo0;
+    for (int d = 0; d < a.wspan; ++d) {
+      const int slot = res * S + quo;
+      u16x8 af[2];
 #pragma unroll
-    for (int ta = 0; ta < 4; ++ta)
+      for (int mt = 0; mt < 2; ++mt)
+        af[mt] = *reinterpret_cast<const u16x8*>(buf + abase + (slot + 16 * mt) * kClCh);
+      // every B fragment of this d is requested before the first MFMA, so
+      // the reads overlap
+      u16x8 bf[G][kNT];
 #pragma unroll
       for (int ph = 0; ph < G; ++ph) {
-        const int dcol = ph < P ? TW.off[jw0 + ph] - cbase : 0;
-        u16x8 af[2], bf[kNT];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-          af[mt] = *reinterpret_cast<const u16x8*>(buf + (apx[mt] + ta * CPX + dcol) * kClCh);
+        const int b = d - dcol[ph];
+        if (b < 0 || b > 3) continue;
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt)
-          bf[nt] = *reinterpret_cast<const u16x8*>(buf + patch_u16 +
-                                                   (((ph * 4 + ta) * kOut + nt * 16 + li) * 4 + g4) * kClCh);
+          bf[ph][nt] = *reinterpret_cast<const u16x8*>(buf + patch_u16 + (((ph * 4 + b) * kNT + nt) * 64 + lane) * kClCh);
+      }
+#pragma unroll
+      for (int ph = 0; ph < G; ++ph) {
+        const int b = d - dcol[ph];
+        if (b < 0 || b > 3) continue;
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-          for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = M::mma(af[mt], bf[nt], acc[ph][mt][nt]);
+          for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = M::mma(af[mt], bf[ph][nt], acc[ph][mt][nt]);
       }
+      if (++res == cstep) {
+        res = 0;
+        ++quo;
+      }
+    }
   };
 
   const int nst = (a.Cin + kClCh - 1) / kClCh;
@@ -335,10 +382,24 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
     }
   }
 
-  // epilogue: 16 output channels at a time through LDS, whole row segments out
-  uint16_t* ob = lds;   // [16][4][32 * P]
+  // epilogue: each wave holds cell row mh0 + wave of every output and phase;
+  // 16 outputs at a time go through the wave's own LDS rows ([output][lw, ph])
+  // and leave as whole row segments of 32 P samples
   const int segw = 32 * P;
-  uint16_t* yout = reinterpret_cast<uint16_t*>(a.y);
+  uint16_t* const ob = lds + wave * (16 * 32 * G);
+  int colrel[3];   // output column of slot lane + 64 k, relative to the segment start
+  bool colok[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int e = lane + 64 * k;
+    const int lw = e / P, ph = e - lw * P;
+    colrel[k] = TW.p * lw + ph;
+    colok[k] = e < segw && mw0 + lw < a.Mw;
+  }
+  const int mh = mh0 + wave;
+  uint16_t* const yrow = reinterpret_cast<uint16_t*>(a.y) +
+                         ((((int64_t)n * a.Cout + o0) * a.Ho + TH.p * mh + jh) * a.Wo + TW.p * mw0 + jw0);
+  const int64_t ostride = (int64_t)a.Ho * a.Wo;
 #pragma unroll
   for (int nt = 0; nt < kNT; ++nt) {
 #pragma unroll
@@ -347,22 +408,20 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int lw = mt * 16 + 4 * g4 + i;   // cell row = wave
-          ob[(li * 4 + wave) * segw + lw * P + ph] = M::to_store(acc[ph][mt][nt][i]);
-        }
+        for (int i = 0; i < 4; ++i)
+          ob[li * segw + (mt * 16 + 4 * g4 + i) * P + ph] = M::to_store(acc[ph][mt][nt][i]);
     }
-    __syncthreads();
-    for (int idx = tid; idx < 16 * 4 * segw; idx += kThreads) {
-      const int row = idx / segw, e = idx - row * segw;
-      const int ol = row >> 2, lh = row & 3;
-      const int lw = e / P, ph = e - lw * P;
-      const int o = o0 + nt * 16 + ol, mh = mh0 + lh, mw = mw0 + lw;
-      if (o < a.Cout && mh < a.Mh && mw < a.Mw)
-        __builtin_nontemporal_store(ob[idx], yout + (((int64_t)n * a.Cout + o) * a.Ho + TH.p * mh + jh) * a.Wo +
-                                                 TW.p * mw + jw0 + ph);
+    fwd::wave_lds_sync();
+    if (mh < a.Mh) {
+      for (int ol = 0; ol < 16; ++ol) {
+        if (o0 + nt * 16 + ol >= a.Cout) break;
+        uint16_t* const rp = yrow + (nt * 16 + ol) * ostride;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (colok[k]) __builtin_nontemporal_store(ob[ol * segw + lane + 64 * k], rp + colrel[k]);
+      }
     }
-    __syncthreads();
+    fwd::wave_lds_sync();
   }
 }
 

@@ -60,6 +60,19 @@ inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); r
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 #define __builtin_nontemporal_load(p) (*(p))
 
+// v_perm_b32: byte i of the result is byte sel[i] of the 8-byte value whose
+// low word is b and high word is a (selectors 0..7 only).
+inline uint32_t __builtin_amdgcn_perm(uint32_t a, uint32_t b, uint32_t sel) {
+  const uint64_t v = ((uint64_t)a << 32) | b;
+  uint32_t r = 0;
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t s = (sel >> (8 * i)) & 0xffu;
+    if (s > 7) std::abort();
+    r |= (uint32_t)((v >> (8 * s)) & 0xffu) << (8 * i);
+  }
+  return r;
+}
+
 // Raw buffer resources: base and record count; reads past the count return 0.
 namespace hostemu {
 struct BufferRsrc {
