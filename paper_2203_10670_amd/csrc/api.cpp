@@ -343,13 +343,14 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
     int CPX = cstep * S + 1;
     CPX += ((16 - CPX) % 32 + 32) % 32;
     const int buf_u16 = 16 * CPX * 8 + P * 4 * kMixOut * 4 * 8;
-#ifndef FCFS_MIX_CL_BUFFERS
-#define FCFS_MIX_CL_BUFFERS 1
-#endif
-    const size_t lds = sizeof(uint16_t) * FCFS_MIX_CL_BUFFERS * (size_t)buf_u16;
+    const size_t lds = sizeof(uint16_t) * (size_t)buf_u16;
     if (Cc + 1 <= 3 * 64 && lds <= 163840 && 2 * c_in * h * w < (int64_t)1 << 31) {
       a.cl = 1;
-      a.xpair = (w % 2 == 0) && (reinterpret_cast<uintptr_t>(x) & 3) == 0;
+      a.xpair = cstep == plan->aw.q && (w % 2 == 0) && (reinterpret_cast<uintptr_t>(x) & 3) == 0;
+      a.fixed = 1;
+      for (int g = 0; g < a.groups; ++g)
+        for (int j = g * P; j < std::min(plan->aw.p, g * P + P); ++j)
+          if (plan->aw.off[j] - plan->aw.off[g * P] != j - g * P) a.fixed = 0;
       a.th_cells = 4;
       a.tw_cells = 32;
       a.rstep = 4;
@@ -360,7 +361,7 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
       a.CP = CPX;
       a.slots = S;
       a.buf_u16 = buf_u16;
-      a.nbuf = FCFS_MIX_CL_BUFFERS;
+      a.nbuf = 1;
       a.lds_bytes = (int)lds;
       a.tiles_h = (a.Mh + 3) / 4;
       a.tiles_w = (a.Mw + 31) / 32;

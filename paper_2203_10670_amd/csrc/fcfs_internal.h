@@ -122,7 +122,8 @@ struct MixArgs {
   int nbuf;                  // LDS stage buffers (2, or 1 when two do not fit)
   int cl;                    // 1: the channel-last kernel (CP counts 16-byte slots of 8 channels)
   int slots;                 // channel-last: slots per residue class of a patch row
-  int xpair;                 // x rows hold aligned pairs of samples (even W, 4-byte aligned x)
+  int xpair;                 // channel-last: pair staging (contiguous patch columns, even W, 4-byte aligned x)
+  int fixed;                 // channel-last: every phase group has consecutive tap column offsets
   int buf_u16, woff_u16;     // LDS stage buffer size and weight offset in it (16-bit units):
                              // patch [2][R][CP], then weights [gsize][32][32] and a spare quad
   AxisTable th, tw_tab;

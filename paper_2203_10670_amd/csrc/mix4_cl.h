@@ -41,15 +41,53 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // format; reads past the record count return zero).
 constexpr int kBufferWord3 = 0x00020000;
 
-template <int DT, int G, int NBUF>
-__global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(const MixArgs a) {
+// The fixed schedule for G phases with tap columns at offsets 0..G-1: blocks
+// (d, phase) for d = 0..G+2 and phase = max(0, d-3)..min(G-1, d), in order.
+template <int G>
+constexpr int fixed_block_d(int i) {
+  for (int d = 0; d < G + 3; ++d) {
+    const int lo = d > 3 ? d - 3 : 0, hi = d < G - 1 ? d : G - 1;
+    if (i <= hi - lo) return d;
+    i -= hi - lo + 1;
+  }
+  return 0;
+}
+template <int G>
+constexpr int fixed_block_ph(int i) {
+  for (int d = 0; d < G + 3; ++d) {
+    const int lo = d > 3 ? d - 3 : 0, hi = d < G - 1 ? d : G - 1;
+    if (i <= hi - lo) return lo + i;
+    i -= hi - lo + 1;
+  }
+  return 0;
+}
+template <int G>
+constexpr bool fixed_block_first(int i) {
+  return i == 0 || fixed_block_d<G>(i) != fixed_block_d<G>(i - 1);
+}
+
+// MODE bit 0: the fixed schedule (every phase group has consecutive tap
+// column offsets); bit 1: pair staging (contiguous patch columns, rows of
+// aligned pairs). Each mode is its own kernel, so each gets its own register
+// allocation.
+template <int DT, int G, int MODE>
+__global__ __launch_bounds__(kThreads, 2) void mix4_cl_kernel(const MixArgs a) {
+  constexpr bool FIXED = (MODE & 1) != 0;
+  constexpr bool PAIRS = (MODE & 2) != 0;
   using M = Mfma<DT>;
   extern __shared__ float smem[];
   uint16_t* const lds = reinterpret_cast<uint16_t*>(smem);
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
 
+  // Block b runs on XCD b % 8; renumbering gives each XCD a contiguous range
+  // of blocks, so the output tiles and phases that share a patch (and the
+  // weights they cycle through) meet in one L2.
   int64_t blk = blockIdx.x;
+  {
+    const int64_t per = (int64_t)gridDim.x / 8;
+    if (blk < 8 * per) blk = (blk % 8) * per + blk / 8;
+  }
   const int otile = (int)(blk % a.otiles); blk /= a.otiles;
   const int group = (int)(blk % a.groups); blk /= a.groups;
   const int jh = (int)(blk % TH.p); blk /= TH.p;
@@ -94,7 +132,7 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
   // whole aligned pairs; pixels whose column lies outside the row are then
   // fixed up from the patch itself.
   const int npx = a.Cc + sh;   // pixels the MFMAs read
-  const bool pairs = contiguous && a.xpair;
+  const bool pairs = PAIRS;   // the host chooses it only for contiguous columns and aligned pairs
   const int pad_left = pairs ? max(0, -cs) : 0;
   const int pad_right = pairs ? max(0, cs + npx - a.W) : 0;
 
@@ -120,21 +158,6 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
     // then 64 consecutive 16-byte chunks, one per lane
     wlds[k] = patch_u16 + (((ph * 4 * kNT + o / 16) * 4) * 16 + o % 16) * kClCh + 2 * cq;
   }
-  uint4 wpre[NBUF == 1 ? 1 : kWItems][4];
-  auto load_w = [&](int cb) {
-    if constexpr (NBUF == 1) return;   // (staged item by item in store_w)
-#pragma unroll
-    for (int k = 0; k < kWItems; ++k) {
-      // each of the two channels only when it exists (the second may be past C_in)
-      const bool ok0 = wok[k] && cb + wch[k] < a.Cin, ok1 = wok[k] && cb + wch[k] + 1 < a.Cin;
-      const uint16_t* src0 = win + (ok0 ? woff[k] + (int64_t)cb * 16 : 0);
-      const uint16_t* src1 = win + (ok1 ? woff[k] + (int64_t)cb * 16 + 16 : 0);
-      wpre[k][0] = *reinterpret_cast<const uint4*>(src0);
-      wpre[k][1] = *reinterpret_cast<const uint4*>(src0 + 8);
-      wpre[k][2] = *reinterpret_cast<const uint4*>(src1);
-      wpre[k][3] = *reinterpret_cast<const uint4*>(src1 + 8);
-    }
-  };
   // Two channels' 16 taps (words of two taps each) become 16 words of one tap
   // and the two channels; only the last stage can hold channels past C_in,
   // which it zeroes (a missing output or phase only feeds results that are
@@ -144,19 +167,19 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
 #pragma unroll
     for (int k = 0; k < kWItems; ++k) {
       if (!wlive[k]) continue;
+      // loaded here, one item at a time (few registers); each of the two
+      // channels from its own row only when it exists
       const bool ok0 = wok[k] && cb + wch[k] < a.Cin, ok1 = wok[k] && cb + wch[k] + 1 < a.Cin;
-      if constexpr (NBUF == 1) {   // loaded here, one item at a time (few registers)
-        const uint16_t* src0 = win + (ok0 ? woff[k] + (int64_t)cb * 16 : 0);
-        const uint16_t* src1 = win + (ok1 ? woff[k] + (int64_t)cb * 16 + 16 : 0);
-        wpre[0][0] = *reinterpret_cast<const uint4*>(src0);
-        wpre[0][1] = *reinterpret_cast<const uint4*>(src0 + 8);
-        wpre[0][2] = *reinterpret_cast<const uint4*>(src1);
-        wpre[0][3] = *reinterpret_cast<const uint4*>(src1 + 8);
-      }
-      const int kk = NBUF == 1 ? 0 : k;
+      const uint16_t* src0 = win + (ok0 ? woff[k] + (int64_t)cb * 16 : 0);
+      const uint16_t* src1 = win + (ok1 ? woff[k] + (int64_t)cb * 16 + 16 : 0);
+      uint4 wv[4];
+      wv[0] = *reinterpret_cast<const uint4*>(src0);
+      wv[1] = *reinterpret_cast<const uint4*>(src0 + 8);
+      wv[2] = *reinterpret_cast<const uint4*>(src1);
+      wv[3] = *reinterpret_cast<const uint4*>(src1 + 8);
       uint32_t w0[8], w1[8];   // channel 2cq and 2cq + 1: 16 taps each
-      __builtin_memcpy(w0, &wpre[kk][0], 32);
-      __builtin_memcpy(w1, &wpre[kk][2], 32);
+      __builtin_memcpy(w0, &wv[0], 32);
+      __builtin_memcpy(w1, &wv[2], 32);
       if (tail) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -182,9 +205,10 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
 #pragma unroll
     for (int j = 0; j < kClPairs; ++j) {
       const int c = min(max(cs + 2 * lane + 128 * j, 0), a.W - 2);   // clamped into the row
-      // a zero-padding row takes a lane offset past the buffer's range, for
-      // which the load returns zero
-      poff[i][j] = sr >= 0 ? 2u * (uint32_t)(sr * a.W + c) : 0x7ffffffcu;
+      // a zero-padding row, or a pair past the patch, takes a lane offset
+      // past the buffer's range, for which the load returns zero without a
+      // memory access
+      poff[i][j] = (sr >= 0 && 2 * lane + 128 * j < npx) ? 2u * (uint32_t)(sr * a.W + c) : 0x7ffffffcu;
     }
   }
   // LDS pixel of each of the lane's two pixels per slot: pixels past the
@@ -292,10 +316,16 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
   // which depends on the phase only through d: one A fragment per d serves
   // every (phase, b) with that d. B fragments are 64 consecutive chunks.
   const int abase = ((4 * wave + g4) * CPX + li) * kClCh;
-  int dcol[G];   // tap column offset of each phase in the group (none past P)
+  int dcol[G];   // tap column offset of each phase in the group (0 past P)
 #pragma unroll
-  for (int ph = 0; ph < G; ++ph) dcol[ph] = ph < P ? TW.off[jw0 + ph] - cbase : -64;
-  const int res0 = sh % cstep, quo0 = sh / cstep;   // class and index of pixel sh + 0 of cell 0
+  for (int ph = 0; ph < G; ++ph) dcol[ph] = ph < P ? TW.off[jw0 + ph] - cbase : 0;
+  // Phases whose tap columns start at consecutive offsets (dcol = phase, as
+  // for 5/4, 4/3, 3/2 and 2/1) share A fragments: column offset d serves the
+  // blocks (phase, d - phase) for phase = max(0, d - 3) .. min(G - 1, d).
+  // slot for cell 0 of column offset d (fixed schedule) or of block (phase, b)
+  int aslot[FIXED ? G + 3 : 4 * G];
+#pragma unroll
+  for (int i = 0; i < (FIXED ? G + 3 : 4 * G); ++i) aslot[i] = slot_of(sh + (FIXED ? i : dcol[i / 4] + i % 4));
   f32x4 acc[G][2][kNT];
 #pragma unroll
   for (int ph = 0; ph < G; ++ph)
@@ -304,82 +334,76 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
 #pragma unroll
       for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  auto compute = [&](const uint16_t* buf) {
-    int res = res0, quo = quo0;
-    for (int d = 0; d < a.wspan; ++d) {
-      const int slot = res * S + quo;
-      u16x8 af[2];
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-        af[mt] = *reinterpret_cast<const u16x8*>(buf + abase + (slot + 16 * mt) * kClCh);
-      // every B fragment of this d is requested before the first MFMA, so
-      // the reads overlap
-      u16x8 bf[G][kNT];
-#pragma unroll
-      for (int ph = 0; ph < G; ++ph) {
-        const int b = d - dcol[ph];
-        if (b < 0 || b > 3) continue;
-#pragma unroll
-        for (int nt = 0; nt < kNT; ++nt)
-          bf[ph][nt] = *reinterpret_cast<const u16x8*>(buf + patch_u16 + (((ph * 4 + b) * kNT + nt) * 64 + lane) * kClCh);
-      }
-#pragma unroll
-      for (int ph = 0; ph < G; ++ph) {
-        const int b = d - dcol[ph];
-        if (b < 0 || b > 3) continue;
+  // A stage is 4 G MFMA blocks (phase, b), each 2 x kNT MFMAs, as
+  // straight-line code: block i's fragments are requested two blocks ahead
+  // into three-slot register rings (scheduling barriers keep that order).
+  // Consecutive offsets run the blocks in order of d with one A fragment per
+  // d; other groups run them phase by phase with an A fragment per block.
+  auto compute = [&](const uint16_t* buf) __attribute__((always_inline)) {
+    constexpr int NB = 4 * G;
+    u16x8 ar[3][2], br[3][kNT];
+    auto load = [&](int i) __attribute__((always_inline)) {
+      const int ph = FIXED ? fixed_block_ph<G>(i) : i / 4;
+      const int b = FIXED ? fixed_block_d<G>(i) - ph : i % 4;
+      if (!FIXED || fixed_block_first<G>(i)) {
+        const int ring = FIXED ? fixed_block_d<G>(i) % 3 : i % 3;
+        const int slot = aslot[FIXED ? fixed_block_d<G>(i) : i];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
+          ar[ring][mt] = *reinterpret_cast<const u16x8*>(buf + abase + (slot + 16 * mt) * kClCh);
+      }
 #pragma unroll
-          for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = M::mma(af[mt], bf[ph][nt], acc[ph][mt][nt]);
-      }
-      if (++res == cstep) {
-        res = 0;
-        ++quo;
-      }
+      for (int nt = 0; nt < kNT; ++nt)
+        br[i % 3][nt] = *reinterpret_cast<const u16x8*>(buf + patch_u16 + (((ph * 4 + b) * kNT + nt) * 64 + lane) * kClCh);
+    };
+    load(0);
+    load(1);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (i + 2 < NB) load(i + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      const int ph = FIXED ? fixed_block_ph<G>(i) : i / 4;
+      const int ring = FIXED ? fixed_block_d<G>(i) % 3 : i % 3;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) acc[ph][mt][nt] = M::mma(ar[ring][mt], br[i % 3][nt], acc[ph][mt][nt]);
+      __builtin_amdgcn_sched_barrier(0);
     }
   };
 
   const int nst = (a.Cin + kClCh - 1) / kClCh;
-  uint16_t* const buf0 = lds;
-  uint16_t* const buf1 = lds + a.buf_u16;
+  // One LDS buffer per stage. Pairs: the next stage's patch loads are issued
+  // before this stage's MFMAs and land after every wave is done with the
+  // stage (another workgroup on the compute unit keeps the matrix cores busy
+  // meanwhile). Samples: each stage is staged, then used.
+  uint16_t* const buf = lds;
+  const bool fix = pairs && pad_left + pad_right > 0;
   if (pairs) {
-    const bool fix = pad_left + pad_right > 0;
     load_patch(0);
-    load_w(0);
-    store_patch(buf0, 0);
-    store_w(buf0, 0);
-    if (fix) fix_pad(buf0, 0);   // disjoint pixels: no barrier between
+    store_patch(buf, 0);
+    store_w(buf, 0);
+    if (fix) fix_pad(buf, 0);   // disjoint pixels: no barrier between
     __syncthreads();
-    for (int s = 0; s < nst; ++s) {
-      // two buffers: the next stage lands in the other one; one buffer: it
-      // lands after every wave is done with this stage (another workgroup on
-      // the compute unit keeps the matrix cores busy meanwhile)
-      uint16_t* cur = (NBUF == 2 && (s & 1)) ? buf1 : buf0;
-      uint16_t* nxt = NBUF == 2 ? ((s & 1) ? buf0 : buf1) : buf0;
-      if (s + 1 < nst) {
-        load_patch(kClCh * (s + 1));
-        load_w(kClCh * (s + 1));
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      compute(cur);
-      __builtin_amdgcn_sched_barrier(0);
-      if (s + 1 < nst) {
-        if (NBUF == 1) __syncthreads();
-        store_patch(nxt, kClCh * (s + 1));
-        store_w(nxt, kClCh * (s + 1));
-        if (fix) fix_pad(nxt, kClCh * (s + 1));
-      }
+  }
+  for (int s = 0; s < nst; ++s) {
+    if (!pairs) {
+      stage_samples(buf, kClCh * s);
+      store_w(buf, kClCh * s);
       __syncthreads();
+    } else if (s + 1 < nst) {
+      load_patch(kClCh * (s + 1));
     }
-  } else {
-    for (int s = 0; s < nst; ++s) {
-      stage_samples(buf0, kClCh * s);
-      load_w(kClCh * s);
-      store_w(buf0, kClCh * s);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(buf);
+    __builtin_amdgcn_sched_barrier(0);
+    if (pairs && s + 1 < nst) {
       __syncthreads();
-      compute(buf0);
-      __syncthreads();
+      store_patch(buf, kClCh * (s + 1));
+      store_w(buf, kClCh * (s + 1));
+      if (fix) fix_pad(buf, kClCh * (s + 1));
     }
+    __syncthreads();
   }
 
   // epilogue: each wave holds cell row mh0 + wave of every output and phase;
@@ -427,8 +451,12 @@ __global__ __launch_bounds__(kThreads, NBUF == 1 ? 2 : 1) void mix4_cl_kernel(co
 
 template <int DT, int G>
 void launch_cl(const MixArgs& a, dim3 grid, hipStream_t stream) {
-  if (a.nbuf == 2) hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 2>), grid, dim3(kThreads), a.lds_bytes, stream, a);
-  else hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 1>), grid, dim3(kThreads), a.lds_bytes, stream, a);
+  switch ((a.fixed ? 1 : 0) | (a.xpair ? 2 : 0)) {
+    case 0: hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 0>), grid, dim3(kThreads), a.lds_bytes, stream, a); break;
+    case 1: hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 1>), grid, dim3(kThreads), a.lds_bytes, stream, a); break;
+    case 2: hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 2>), grid, dim3(kThreads), a.lds_bytes, stream, a); break;
+    default: hipLaunchKernelGGL((mix4_cl_kernel<DT, G, 3>), grid, dim3(kThreads), a.lds_bytes, stream, a); break;
+  }
 }
 
 }  // namespace mix
