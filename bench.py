@@ -194,7 +194,28 @@ def measure_rows(reps: int):
                                            "fwd_bytes": bf, "bwd_bytes": bb}
         del sets, ws
         torch.cuda.empty_cache()
+    out["quality_vs_framework_resize"] = measure_quality()
     return out
+
+
+def measure_quality():
+    """PSNR / SSIM of the FCFS output against torch's interpolate (same
+    half-pixel grid, edge clamping) on the smooth synthetic set S
+    (4 x 3 x 512^2), replicate padding, for up- and down-scaling factors
+    including the paper's 27/11 and 2/11."""
+    import torch
+    import paper_2203_10670_amd as fc
+    from paper_2203_10670_amd import quality
+    import synth
+    x = torch.from_numpy(synth.smooth(3, (4, 3, 512, 512))).cuda()
+    rows = {}
+    for p, q in ((3, 2), (5, 4), (2, 1), (27, 11), (2, 3), (4, 5), (1, 2), (2, 11)):
+        for m in ("nearest", "bilinear", "bicubic"):
+            y = fc.resize(x, p, q, m, "replicate")
+            ps, ss = quality.compare_with_framework(y, x, p, q, m)
+            rows["%d/%d %s" % (p, q, m)] = {"psnr_db": None if ps == float("inf") else round(ps, 2),
+                                            "ssim": round(ss, 6)}
+    return rows
 
 
 def measure_serving(count: int, rhos=(0.25, 0.5, 0.8, 0.95)):
