@@ -194,7 +194,59 @@ def measure_rows(reps: int):
                                            "fwd_bytes": bf, "bwd_bytes": bb}
         del sets, ws
         torch.cuda.empty_cache()
+    out.update(measure_nd(reps))
     out["quality_vs_framework_resize"] = measure_quality()
+    return out
+
+
+def measure_nd(reps: int):
+    """1D and 3D FCFS, FP32 bicubic reflect: 16 x 2 signals of 2^20 samples
+    at 3/2 (one pass), and a 2 x 1 x 128 x 256 x 256 volume at 3/2 on every
+    axis (two passes through a workspace). GB/s counts the input and output
+    once; the 3D figure with the intermediate's write and read is given too."""
+    import torch
+    import paper_2203_10670_amd as fc
+    import synth
+    dev = torch.device("cuda:0")
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    out = {}
+
+    def timeit(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1000.0 / n
+
+    N, C, L = 16, 2, 1 << 20
+    x1 = torch.from_numpy(synth.normal(40, (N, C, L))).to(dev)
+    pl1 = fc.Plan(1, 1, "bicubic", "reflect", pw=3, qw=2)
+    lo = pl1.output_size(1, L)[1]
+    y1 = torch.empty((N, C, lo), device=dev)
+    us = timeit(lambda: fc.fcfs_forward_1d(pl1.handle, 0, N, C, L, x1.data_ptr(), y1.data_ptr(), sp), reps)
+    b = (N * C * L + N * C * lo) * 4
+    out["nd_1d_3_2_16x2x1M_f32"] = {"us": round(us, 2), "bytes": b, "GBps": round(b / us / 1e3, 1)}
+    del x1, y1
+    n, c, d, h, w = 2, 1, 128, 256, 256
+    x3 = torch.from_numpy(synth.normal(41, (n, c, d, h, w))).to(dev)
+    pld = fc.Plan(3, 2, "bicubic", "reflect", pw=1, qw=1)
+    plhw = fc.Plan(3, 2, "bicubic", "reflect")
+    do = pld.output_size(d, 1)[0]
+    ho, wo = plhw.output_size(h, w)
+    y3 = torch.empty((n, c, do, ho, wo), device=dev)
+    wsb = fc.fcfs_forward_3d_workspace(pld.handle, plhw.handle, 0, n, c, d, h, w)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    us = timeit(lambda: fc.fcfs_forward_3d(pld.handle, plhw.handle, 0, n, c, d, h, w, x3.data_ptr(), y3.data_ptr(),
+                                           ws.data_ptr(), wsb, sp), reps)
+    b = (n * c * d * h * w + n * c * do * ho * wo) * 4
+    out["nd_3d_3_2_2x1x128x256x256_f32"] = {"us": round(us, 2), "bytes": b, "GBps": round(b / us / 1e3, 1),
+                                            "GBps_with_intermediate": round((b + 2 * wsb) / us / 1e3, 1)}
+    del x3, y3, ws
+    torch.cuda.empty_cache()
     return out
 
 
@@ -325,15 +377,17 @@ def _counter_rows(d, counter):
 
 
 def _kernel_id(name):
-    """Instance id of a forward kernel name fcfs_fwd_kernel<DT, T, KC, L, LEARNED, PAIR>
-    (as fcfs_forward_config reports it)."""
+    """Instance id of a forward kernel name fcfs_fwd_kernel<DT, T, KC, L, LEARNED,
+    PAIR, TV> (as fcfs_forward_config reports it; T width taps, TV height taps)."""
     import re
-    m = re.search(r"fcfs_fwd_kernel<(\d+), (\d+), (\d+), (\d+), (true|false)(?:, (true|false))?>", name)
+    m = re.search(r"fcfs_fwd_kernel<(\d+), (\d+), (\d+), (\d+), (true|false)(?:, (true|false))?(?:, (\d+))?>",
+                  name)
     if not m:
         return None
     dt, t, kc, sl = (int(m.group(i)) for i in range(1, 5))
-    return (dt * 1000 + t * 100 + kc * 10 + sl + (10000 if m.group(5) == "true" else 0) +
-            (50000 if m.group(6) == "true" else 0))
+    tv = int(m.group(7)) if m.group(7) else t
+    return (dt * 1000 + max(t, tv) * 100 + kc * 10 + sl + (10000 if m.group(5) == "true" else 0) +
+            (50000 if m.group(6) == "true" else 0) + (100000 if tv < t else 0) + (200000 if t < tv else 0))
 
 
 def write_traffic(fetch_dir, write_dir):

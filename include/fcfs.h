@@ -99,8 +99,9 @@ fcfs_status fcfs_plan_ex(int p_h, int q_h, int p_w, int q_w, fcfs_method method,
 /* Free a plan. NULL is accepted. */
 fcfs_status fcfs_plan_destroy(fcfs_plan_t plan);
 
-/* Reduced factors of the height axis and taps per axis (1, 2 or 4). Any
- * output pointer may be NULL. */
+/* Reduced factors of the height axis and the method's taps per axis (1, 2
+ * or 4; an axis at 1/1 that samples its inputs exactly copies them with one
+ * tap, see fcfs_plan_taps). Any output pointer may be NULL. */
 fcfs_status fcfs_plan_query(fcfs_plan_t plan, int* p_red, int* q_red, int* taps);
 
 /* Tap table of one phase (Sec. 3.1.1: phase j of every cell m interpolates
@@ -137,6 +138,41 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
                          int64_t w, const void* x, const void* weight, int64_t c_out, void* y,
                          hipStream_t stream);
 
+/* One-dimensional FCFS (Sec. 3.1; signals such as audio): x [n][c][l] ->
+ * y [n][c][p * ceil(l / q)], where p/q is the plan's width factor. The plan's
+ * height factor must be 1/1 (fcfs_plan_ex(1, 1, p, q, ...)), whose axis then
+ * copies rows with one tap: the n*c signals run as the rows of one plane
+ * (or, past 2^31 samples, as planes of one row) of fcfs_forward.
+ * Fixed methods only. Errors: FCFS_E_INVAL for a height factor other than
+ * 1/1 or a learned method, FCFS_E_UNSUPPORTED for FCFS_GRID_PAPER (its 1/1
+ * axis samples half-way between rows, not the row), else as fcfs_forward. */
+fcfs_status fcfs_forward_1d(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c, int64_t l,
+                            const void* x, void* y, hipStream_t stream);
+
+/* Three-dimensional FCFS (Sec. 4.2 with the ND pixelshuffle of Sec. 4.1;
+ * volumes such as medical scans) of NCDHW tensors for the fixed methods:
+ *   plan_d  : the depth factor as its height factor, width factor 1/1
+ *             (fcfs_plan_ex(p_d, q_d, 1, 1, method, pad, grid));
+ *   plan_hw : the height and width factors (fcfs_plan_ex(p_h, q_h, p_w, q_w,
+ *             method, pad, grid)), with the same method, padding and grid.
+ *   x : device [n][c][d][h][w] of dtype; y : device [n][c][d_out][h_out][w_out].
+ * The interpolants are separable, so the result is two passes of the fused
+ * forward kernel through a device workspace (the smaller of the two possible
+ * intermediates: [n][c][d][h_out][w_out] after the height-width pass, or
+ * [n][c][d_out][h][w] after the depth pass), each pass exact up to rounding;
+ * with 16-bit storage the intermediate is rounded to the storage type too.
+ * The workspace is caller-owned, at least fcfs_forward_3d_workspace bytes,
+ * 4-byte aligned, and must not overlap x or y.
+ * Errors: FCFS_E_INVAL (null pointers, mismatched plans, a learned method,
+ * a depth plan whose width factor is not 1/1, a small workspace),
+ * FCFS_E_UNSUPPORTED for FCFS_GRID_PAPER (the depth pass's 1/1 width axis
+ * would not copy), else as fcfs_forward. */
+fcfs_status fcfs_forward_3d_workspace(fcfs_plan_t plan_d, fcfs_plan_t plan_hw, fcfs_dtype dtype, int64_t n,
+                                      int64_t c, int64_t d, int64_t h, int64_t w, size_t* bytes);
+fcfs_status fcfs_forward_3d(fcfs_plan_t plan_d, fcfs_plan_t plan_hw, fcfs_dtype dtype, int64_t n, int64_t c,
+                            int64_t d, int64_t h, int64_t w, const void* x, void* y, void* workspace,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* Launch geometry fcfs_forward would use for these sizes (introspection for
  * tests and benchmarks; enqueues nothing). kernel_id identifies the compiled
  * kernel instance: dtype*1000 + taps*100 + column groups per lane*10 + staged
@@ -144,7 +180,8 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
  * channel-mixing layer, 50000 for the paired 16-bit instance, where the last
  * digit counts staged sample pairs; fcfs_forward takes that instance when
  * both widths are even and x and y are 4-byte aligned, which this call
- * assumes). Any output pointer may be NULL. Errors: as fcfs_forward's
+ * assumes; 100000 when the height axis is a 1/1 copy with one tap beside a
+ * resampled width, 200000 for the reverse; taps is the larger count). Any output pointer may be NULL. Errors: as fcfs_forward's
  * argument checks. */
 fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
                                 int64_t h, int64_t w, int* kernel_id, int* strip_width,

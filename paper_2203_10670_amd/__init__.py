@@ -85,6 +85,9 @@ _sig("fcfs_output_size", [_P, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_
 _sig("fcfs_forward", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P])
 _sig("fcfs_forward_config", [_P, _I, _I64, _I64, _I64, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I),
                              ctypes.POINTER(_I), ctypes.POINTER(_I64)])
+_sig("fcfs_forward_1d", [_P, _I, _I64, _I64, _I64, _P, _P, _P])
+_sig("fcfs_forward_3d_workspace", [_P, _P, _I, _I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)])
+_sig("fcfs_forward_3d", [_P, _P, _I, _I64, _I64, _I64, _I64, _I64, _P, _P, _P, _SZ, _P])
 _sig("fcfs_backward_workspace", [_P, _I, _I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)])
 _sig("fcfs_backward", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P])
 
@@ -180,6 +183,21 @@ def fcfs_forward_config(plan, dtype, n, c_in, h, w):
     _check(lib.fcfs_forward_config(plan, dtype, n, c_in, h, w, ctypes.byref(k), ctypes.byref(tw),
                                    ctypes.byref(bc), ctypes.byref(wv)), "fcfs_forward_config")
     return k.value, tw.value, bc.value, wv.value
+
+
+def fcfs_forward_1d(plan, dtype, n, c, l, x_ptr, y_ptr, stream) -> int:
+    return lib.fcfs_forward_1d(plan, dtype, n, c, l, x_ptr, y_ptr, stream)
+
+
+def fcfs_forward_3d_workspace(plan_d, plan_hw, dtype, n, c, d, h, w) -> int:
+    b = _SZ()
+    _check(lib.fcfs_forward_3d_workspace(plan_d, plan_hw, dtype, n, c, d, h, w, ctypes.byref(b)),
+           "fcfs_forward_3d_workspace")
+    return b.value
+
+
+def fcfs_forward_3d(plan_d, plan_hw, dtype, n, c, d, h, w, x_ptr, y_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib.fcfs_forward_3d(plan_d, plan_hw, dtype, n, c, d, h, w, x_ptr, y_ptr, ws_ptr, ws_bytes, stream)
 
 
 def fcfs_backward_workspace(plan, dtype, n, c_in, h, w, c_out) -> int:
@@ -424,6 +442,38 @@ def resize(x, p: int, q: int, method: str = "bilinear", pad: str = "replicate", 
            weight=None, pw: int | None = None, qw: int | None = None):
     """Rescale an NCHW device tensor by p/q (and pw/qw on the width axis)."""
     return _cached_plan(p, q, method, pad, grid, pw, qw).forward(x.contiguous(), weight)
+
+
+def resize1d(x, p: int, q: int, method: str = "bilinear", pad: str = "replicate", grid: str = "half"):
+    """Rescale an NCL device tensor (1D signals) by p/q."""
+    torch = _torch()
+    x = x.contiguous()
+    n, c, l = x.shape
+    pl = _cached_plan(1, 1, method, pad, grid, p, q)
+    lo = pl.output_size(1, l)[1]
+    y = torch.empty((n, c, lo), dtype=x.dtype, device=x.device)
+    _check(fcfs_forward_1d(pl.handle, _dtype_code(x), n, c, l, _dev_ptr(x), _dev_ptr(y), _stream_ptr(x.device)),
+           "fcfs_forward_1d")
+    return y
+
+
+def resize3d(x, factors, method: str = "bilinear", pad: str = "replicate", grid: str = "half"):
+    """Rescale an NCDHW device tensor by ``factors`` = ((p_d, q_d), (p_h, q_h), (p_w, q_w))."""
+    torch = _torch()
+    x = x.contiguous()
+    n, c, d, h, w = x.shape
+    (pd, qd), (ph, qh), (pw, qw) = factors
+    pl_d = _cached_plan(pd, qd, method, pad, grid, 1, 1)
+    pl_hw = _cached_plan(ph, qh, method, pad, grid, pw, qw)
+    do = pl_d.output_size(d, 1)[0]
+    ho, wo = pl_hw.output_size(h, w)
+    code = _dtype_code(x)
+    y = torch.empty((n, c, do, ho, wo), dtype=x.dtype, device=x.device)
+    wsb = fcfs_forward_3d_workspace(pl_d.handle, pl_hw.handle, code, n, c, d, h, w)
+    ws = torch.empty(max(wsb, 4), dtype=torch.uint8, device=x.device)
+    _check(fcfs_forward_3d(pl_d.handle, pl_hw.handle, code, n, c, d, h, w, _dev_ptr(x), _dev_ptr(y),
+                           _dev_ptr(ws), wsb, _stream_ptr(x.device)), "fcfs_forward_3d")
+    return y
 
 
 def _make_function():

@@ -229,12 +229,8 @@ fcfs_status fcfs_plan_ex(int p_h, int q_h, int p_w, int q_w, fcfs_method method,
   pl->grid = grid;
   fcfs_status st = build_axis(p_h, q_h, method, grid, true, &pl->ah);
   if (st == FCFS_OK) st = build_axis(p_w, q_w, method, grid, true, &pl->aw);
-  if (st == FCFS_OK && pl->ah.T != pl->aw.T) {
-    // Only the 1/1 copy shortcut makes the axes differ: the kernel takes one
-    // tap count, so give both axes the method's full taps.
-    st = build_axis(p_h, q_h, method, grid, false, &pl->ah);
-    if (st == FCFS_OK) st = build_axis(p_w, q_w, method, grid, false, &pl->aw);
-  }
+  // (Only the 1/1 copy shortcut makes the axes' tap counts differ; the
+  // forward kernel has instances for a copying height or width axis.)
   if (st != FCFS_OK) {
     delete pl;
     return st;
@@ -256,7 +252,7 @@ fcfs_status fcfs_plan_query(fcfs_plan_t plan, int* p_red, int* q_red, int* taps)
   if (!plan) return FCFS_E_INVAL;
   if (p_red) *p_red = plan->ah.p;
   if (q_red) *q_red = plan->ah.q;
-  if (taps) *taps = plan->ah.T;
+  if (taps) *taps = std::max(plan->ah.T, plan->aw.T);
   return FCFS_OK;
 }
 
@@ -461,6 +457,93 @@ fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t 
   }
 }
 
+fcfs_status fcfs_forward_1d(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c, int64_t l,
+                            const void* x, void* y, hipStream_t stream) {
+  if (!plan) return FCFS_E_INVAL;
+  if (plan->ah.p != 1 || plan->ah.q != 1) return FCFS_E_INVAL;
+  if (plan->method == FCFS_LEARNED_DW4 || plan->method == FCFS_LEARNED_MIX4) return FCFS_E_INVAL;
+  // the 1/1 height axis must sample its row exactly, which the paper grid's
+  // half-sample offset does not
+  if (plan->grid == FCFS_GRID_PAPER) return FCFS_E_UNSUPPORTED;
+  if (n < 0 || c < 0 || l < 0) return FCFS_E_INVAL;
+  // The height axis copies its rows, so the n*c signals can be the rows of
+  // one plane (streamed in bands like an image) while that plane fits the
+  // kernel's 32-bit in-plane indexing; else one row per plane.
+  const int64_t wo = plan->aw.p * ((l + plan->aw.q - 1) / plan->aw.q);
+  if (n * c * std::max(l, wo) < ((int64_t)1 << 31))
+    return fcfs_forward(plan, dtype, 1, 1, n * c, l, x, nullptr, 1, y, stream);
+  return fcfs_forward(plan, dtype, n, c, 1, l, x, nullptr, c, y, stream);
+}
+
+namespace {
+
+// The two passes of a 3D forward: which one runs first and the intermediate's
+// elements. HW first leaves [n][c][d][h_out][w_out]; D first [n][c][d_out][h][w].
+struct Plan3d {
+  int64_t d_out, h_out, w_out;
+  bool hw_first;
+  int64_t inter;
+};
+
+fcfs_status plan_3d(fcfs_plan_t plan_d, fcfs_plan_t plan_hw, fcfs_dtype dtype, int64_t n, int64_t c, int64_t d,
+                    int64_t h, int64_t w, Plan3d* o) {
+  if (!plan_d || !plan_hw) return FCFS_E_INVAL;
+  if ((int)dtype < FCFS_F32 || (int)dtype > FCFS_F16) return FCFS_E_INVAL;
+  if (n < 0 || c < 0 || d < 0 || h < 0 || w < 0) return FCFS_E_INVAL;
+  const auto learned = [](fcfs_plan_t p) {
+    return p->method == FCFS_LEARNED_DW4 || p->method == FCFS_LEARNED_MIX4;
+  };
+  if (learned(plan_d) || learned(plan_hw)) return FCFS_E_INVAL;
+  if (plan_d->method != plan_hw->method || plan_d->pad != plan_hw->pad || plan_d->grid != plan_hw->grid)
+    return FCFS_E_INVAL;
+  if (plan_d->aw.p != 1 || plan_d->aw.q != 1) return FCFS_E_INVAL;
+  // the depth pass's 1/1 width axis must copy, which the paper grid's
+  // half-sample offset does not
+  if (plan_d->grid == FCFS_GRID_PAPER) return FCFS_E_UNSUPPORTED;
+  const int64_t pd = plan_d->ah.p, qd = plan_d->ah.q;
+  o->d_out = pd * ((d + qd - 1) / qd);
+  o->h_out = plan_hw->ah.p * ((h + plan_hw->ah.q - 1) / plan_hw->ah.q);
+  o->w_out = plan_hw->aw.p * ((w + plan_hw->aw.q - 1) / plan_hw->aw.q);
+  const int64_t a = n * c * d * o->h_out * o->w_out, b = n * c * o->d_out * h * w;
+  o->hw_first = a <= b;
+  o->inter = o->hw_first ? a : b;
+  return FCFS_OK;
+}
+
+}  // namespace
+
+fcfs_status fcfs_forward_3d_workspace(fcfs_plan_t plan_d, fcfs_plan_t plan_hw, fcfs_dtype dtype, int64_t n,
+                                      int64_t c, int64_t d, int64_t h, int64_t w, size_t* bytes) {
+  if (!bytes) return FCFS_E_INVAL;
+  *bytes = 0;
+  Plan3d g;
+  fcfs_status st = plan_3d(plan_d, plan_hw, dtype, n, c, d, h, w, &g);
+  if (st != FCFS_OK) return st;
+  *bytes = (size_t)g.inter * (dtype == FCFS_F32 ? 4 : 2);
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward_3d(fcfs_plan_t plan_d, fcfs_plan_t plan_hw, fcfs_dtype dtype, int64_t n, int64_t c,
+                            int64_t d, int64_t h, int64_t w, const void* x, void* y, void* workspace,
+                            size_t ws_bytes, hipStream_t stream) {
+  Plan3d g;
+  fcfs_status st = plan_3d(plan_d, plan_hw, dtype, n, c, d, h, w, &g);
+  if (st != FCFS_OK) return st;
+  if (n == 0 || c == 0 || d == 0 || h == 0 || w == 0) return FCFS_OK;
+  if (!x || !y || !workspace) return FCFS_E_INVAL;
+  if (ws_bytes < (size_t)g.inter * (dtype == FCFS_F32 ? 4 : 2)) return FCFS_E_INVAL;
+  if (g.hw_first) {
+    // planes [n*c*d][h][w] -> workspace [n*c][d][h_out*w_out] -> y [n*c][d_out][h_out*w_out]
+    st = fcfs_forward(plan_hw, dtype, n * c * d, 1, h, w, x, nullptr, 1, workspace, stream);
+    if (st != FCFS_OK) return st;
+    return fcfs_forward(plan_d, dtype, n * c, 1, d, g.h_out * g.w_out, workspace, nullptr, 1, y, stream);
+  }
+  // [n*c][d][h*w] -> workspace [n*c][d_out][h*w] = planes [n*c*d_out][h][w] -> y
+  st = fcfs_forward(plan_d, dtype, n * c, 1, d, h * w, x, nullptr, 1, workspace, stream);
+  if (st != FCFS_OK) return st;
+  return fcfs_forward(plan_hw, dtype, n * c * g.d_out, 1, h, w, workspace, nullptr, 1, y, stream);
+}
+
 fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
                                 int64_t h, int64_t w, int* kernel_id, int* strip_width,
                                 int* band_cells, int64_t* waves) {
@@ -475,8 +558,10 @@ fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
     st = plan_forward_geom(plan, dtype, n * c_in, (int)h, (int)w, (int)ho, (int)wo, pair_ok, &g);
     if (st != FCFS_OK) return st;
   }
-  int id = (int)dtype * 1000 + plan->ah.T * 100 + g.kc * 10 + g.slots;
+  int id = (int)dtype * 1000 + std::max(plan->ah.T, plan->aw.T) * 100 + g.kc * 10 + g.slots;
   if (g.paired) id += 50000;
+  if (plan->ah.T < plan->aw.T) id += 100000;   // the height axis copies
+  if (plan->aw.T < plan->ah.T) id += 200000;   // the width axis copies
   if (plan->method == FCFS_LEARNED_DW4) id += 10000;
   if (plan->method == FCFS_LEARNED_MIX4) id += 20000;
   if (kernel_id) *kernel_id = id;

@@ -147,11 +147,15 @@ __device__ __forceinline__ int strip_first_column(const FwdArgs& a, int64_t wid)
 // segment wholly inside the row): every lane loads and stores two adjacent
 // samples as one dword; its output columns are the adjacent pairs
 // ow0 + 2*lane + 128*g + {0, 1}.
-template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false>
+// T: width taps; TV: height taps (equal, except that an axis at 1/1 which
+// samples its inputs exactly copies them with one tap while the other axis
+// keeps the method's taps).
+template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false, int TV = T>
 __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslot, int lane, float* smem) {
   using S = Store<DT>;
   using TS = typename S::T;
   static_assert(!PAIR || (DT != FCFS_F32 && KC % 2 == 0 && L <= 4), "paired I/O: 16-bit, column pairs");
+  static_assert(!LEARNED || TV == T, "learned taps on both axes");
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
 
@@ -244,14 +248,14 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
     frho = (frho + 1 == TH.q) ? 0 : frho + 1;
   };
 
-  // FIFO of the last T rows: fixed methods keep the width-filtered value per
+  // FIFO of the last TV rows: fixed methods keep the width-filtered value per
   // column, the learned variant the T raw taps per column.
   constexpr int FT = LEARNED ? T : 1;
-  float fifo[KC][T][FT];
+  float fifo[KC][TV][FT];
 #pragma unroll
   for (int c = 0; c < KC; ++c)
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int t = 0; t < TV; ++t)
 #pragma unroll
       for (int b = 0; b < FT; ++b) fifo[c][t][b] = 0.f;
 
@@ -297,11 +301,11 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
-      for (int t = 0; t + 1 < T; ++t)
+      for (int t = 0; t + 1 < TV; ++t)
 #pragma unroll
         for (int b = 0; b < FT; ++b) fifo[c][t][b] = fifo[c][t + 1][b];
 #pragma unroll
-      for (int b = 0; b < FT; ++b) fifo[c][T - 1][b] = cur[c][b];
+      for (int b = 0; b < FT; ++b) fifo[c][TV - 1][b] = cur[c][b];
     }
 
     // Finish every output row whose last height tap is this row.
@@ -324,7 +328,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
             for (int b = 0; b < T; ++b) acc = __builtin_fmaf(wk[t * 4 + b], fifo[c][t][b], acc);
           outv[c] = acc;
         }
-      } else if constexpr (T == 1) {
+      } else if constexpr (TV == 1) {
 #pragma unroll
         for (int c = 0; c < KC; ++c) outv[c] = fifo[c][0][0];
       } else {
@@ -332,7 +336,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
         for (int c = 0; c < KC; ++c) {
           float acc = er.w[0] * fifo[c][0][0];
 #pragma unroll
-          for (int t = 1; t < T; ++t) acc = __builtin_fmaf(er.w[t], fifo[c][t][0], acc);
+          for (int t = 1; t < TV; ++t) acc = __builtin_fmaf(er.w[t], fifo[c][t][0], acc);
           outv[c] = acc;
         }
       }
@@ -369,7 +373,7 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
   }
 }
 
-template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false>
+template <int DT, int T, int KC, int L, bool LEARNED, bool PAIR = false, int TV = T>
 __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63;
@@ -390,14 +394,14 @@ __global__ __launch_bounds__(256) void fcfs_fwd_kernel(const FwdArgs a) {
     // strips whose staged segment reaches past either end of the row (and so
     // needs padding) move single samples
     const int cs = strip_first_column<true>(a, wid);
-    if (cs < 0 || cs + 128 * L > a.W) fwd_wave<DT, T, KC, 2 * L, LEARNED, false>(a, wid, wslot, lane, smem);
-    else fwd_wave<DT, T, KC, L, LEARNED, true>(a, wid, wslot, lane, smem);
+    if (cs < 0 || cs + 128 * L > a.W) fwd_wave<DT, T, KC, 2 * L, LEARNED, false, TV>(a, wid, wslot, lane, smem);
+    else fwd_wave<DT, T, KC, L, LEARNED, true, TV>(a, wid, wslot, lane, smem);
   } else {
-    fwd_wave<DT, T, KC, L, LEARNED, false>(a, wid, wslot, lane, smem);
+    fwd_wave<DT, T, KC, L, LEARNED, false, TV>(a, wid, wslot, lane, smem);
   }
 }
 
-template <int DT, int T, int KC, bool LEARNED>
+template <int DT, int T, int KC, bool LEARNED, int TV = T>
 fcfs_status launch_l(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
   const dim3 block(64 * kWaves);
   const dim3 grid((unsigned)((g.waves + kWaves - 1) / kWaves));
@@ -405,35 +409,40 @@ fcfs_status launch_l(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
   if (LEARNED) lds += sizeof(float) * kWaves * a.th.p * a.tw_tab.p * 16;
   if constexpr (DT != FCFS_F32 && !LEARNED && KC % 2 == 0) {
     if (g.paired) {
-      if (g.slots <= 2) hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED, true>), grid, block, lds, stream, a);
-      else hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED, true>), grid, block, lds, stream, a);
+      if (g.slots <= 2) hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED, true, TV>), grid, block, lds, stream, a);
+      else hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED, true, TV>), grid, block, lds, stream, a);
       return hipGetLastError() == hipSuccess ? FCFS_OK : FCFS_E_DEVICE;
     }
   }
   switch (g.slots) {
-    case 2: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED>), grid, block, lds, stream, a); break;
-    case 4: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED>), grid, block, lds, stream, a); break;
-    default: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 8, LEARNED>), grid, block, lds, stream, a); break;
+    case 2: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 2, LEARNED, false, TV>), grid, block, lds, stream, a); break;
+    case 4: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 4, LEARNED, false, TV>), grid, block, lds, stream, a); break;
+    default: hipLaunchKernelGGL((fcfs_fwd_kernel<DT, T, KC, 8, LEARNED, false, TV>), grid, block, lds, stream, a); break;
   }
   return hipGetLastError() == hipSuccess ? FCFS_OK : FCFS_E_DEVICE;
 }
 
-template <int DT, int T>
+template <int DT, int T, int TV = T>
 fcfs_status launch_kc(const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
   switch (g.kc) {
-    case 4: return launch_l<DT, T, 4, false>(a, g, stream);
-    case 2: return launch_l<DT, T, 2, false>(a, g, stream);
-    default: return launch_l<DT, T, 1, false>(a, g, stream);
+    case 4: return launch_l<DT, T, 4, false, TV>(a, g, stream);
+    case 2: return launch_l<DT, T, 2, false, TV>(a, g, stream);
+    default: return launch_l<DT, T, 1, false, TV>(a, g, stream);
   }
 }
 
 template <int DT>
 fcfs_status launch_forward_dt(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream) {
   if (method == FCFS_LEARNED_DW4) return launch_l<DT, 4, 1, true>(a, g, stream);
-  switch (a.th.T) {
-    case 1: return launch_kc<DT, 1>(a, g, stream);
-    case 2: return launch_kc<DT, 2>(a, g, stream);
-    default: return launch_kc<DT, 4>(a, g, stream);
+  switch (a.tw_tab.T * 10 + a.th.T) {
+    case 11: return launch_kc<DT, 1>(a, g, stream);
+    case 22: return launch_kc<DT, 2>(a, g, stream);
+    case 44: return launch_kc<DT, 4>(a, g, stream);
+    case 21: return launch_kc<DT, 2, 1>(a, g, stream);   // height axis copies
+    case 41: return launch_kc<DT, 4, 1>(a, g, stream);
+    case 12: return launch_kc<DT, 1, 2>(a, g, stream);   // width axis copies
+    case 14: return launch_kc<DT, 1, 4>(a, g, stream);
+    default: return FCFS_E_UNSUPPORTED;
   }
 }
 

@@ -73,6 +73,18 @@ def test_paired_16bit_io():
     _run(cases)
 
 
+def test_copy_axis_beside_resampled_axis():
+    # a 1/1 axis copies with one tap while the other keeps the method's taps
+    # (the instances with separate height and width tap counts)
+    cases = []
+    for (p, q, pw, qw) in [(1, 1, 3, 2), (1, 1, 2, 7), (5, 4, 1, 1), (2, 3, 1, 1)]:
+        for m in ["bilinear", "bicubic"]:
+            cases.append({"p": p, "q": q, "pw": pw, "qw": qw, "method": m, "pad": "reflect", "shape": [1, 2, 21, 150]})
+    cases.append({"p": 1, "q": 1, "pw": 3, "qw": 2, "method": "bicubic", "pad": "zero", "dtype": "bf16",
+                  "shape": [1, 1, 12, 130]})
+    _run(cases)
+
+
 def test_grids_anisotropic_degenerate():
     _run([{"p": 3, "q": 2, "pw": 4, "qw": 5, "method": "bicubic", "pad": "zero", "shape": [1, 1, 19, 80]},
           {"p": 3, "q": 2, "method": "bilinear", "pad": "reflect", "grid": "paper", "shape": [1, 1, 12, 40]},

@@ -111,10 +111,18 @@ def test_output_size_matches_oracle(p, q):
 def test_anisotropic_plan():
     pl = fc.Plan(3, 2, "bicubic", "reflect", pw=5, qw=4)
     assert pl.output_size(10, 16) == (15, 20)
-    # an axis at 1/1 next to a resampled one keeps the method's four taps
+    # an axis at 1/1 next to a resampled one copies with one tap (the other
+    # keeps the method's four), on the grids that sample inputs exactly
     pl = fc.Plan(1, 1, "bicubic", "reflect", pw=3, qw=2)
     assert pl.taps == 4
-    assert fc.fcfs_plan_taps(pl.handle, 0, 0)[1] == [0.0, 1.0, 0.0, 0.0]
+    assert fc.fcfs_plan_taps(pl.handle, 0, 0) == (0, [1.0, 0.0, 0.0, 0.0])
+    assert fc.fcfs_forward_config(pl.handle, 0, 1, 1, 64, 4096)[0] // 100000 == 1
+    pl = fc.Plan(3, 2, "bilinear", "zero", pw=1, qw=1)
+    assert fc.fcfs_plan_taps(pl.handle, 1, 0) == (0, [1.0, 0.0, 0.0, 0.0])
+    assert fc.fcfs_forward_config(pl.handle, 0, 1, 1, 64, 4096)[0] // 100000 == 2
+    # the paper grid's 1/1 axis interpolates half-way between samples: no copy
+    pl = fc.Plan(1, 1, "bicubic", "reflect", "paper", pw=3, qw=2)
+    assert fc.fcfs_plan_taps(pl.handle, 0, 0)[1] != [1.0, 0.0, 0.0, 0.0]
 
 
 def test_request_structs_match_header(tmp_path):
@@ -152,3 +160,36 @@ def test_one_hip_runtime_with_torch():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.startswith("1 "), out.stdout
+
+
+def test_nd_entry_points_validate_without_gpu():
+    # 1D: the plan's height factor must be 1/1, fixed methods, not the paper grid
+    one = fc.fcfs_plan_ex(1, 1, 3, 2, 2, 2, 0)
+    assert fc.fcfs_forward_1d(one, 0, 0, 3, 100, None, None, None) == fc.OK        # empty: no-op
+    assert fc.fcfs_forward_1d(one, 0, 1, 3, 100, None, None, None) == fc.E_INVAL   # null pointers
+    two = fc.fcfs_plan_ex(3, 2, 3, 2, 2, 2, 0)
+    assert fc.fcfs_forward_1d(two, 0, 1, 3, 100, 16, 16, None) == fc.E_INVAL
+    paper = fc.fcfs_plan_ex(1, 1, 3, 2, 1, 2, 1)
+    assert fc.fcfs_forward_1d(paper, 0, 1, 3, 100, 16, 16, None) == fc.E_UNSUPPORTED
+    # 3D: depth plan with a 1/1 width axis, matching method / pad / grid
+    pd = fc.fcfs_plan_ex(3, 2, 1, 1, 2, 2, 0)
+    phw = fc.fcfs_plan_ex(5, 4, 2, 3, 2, 2, 0)
+    n, c, d, h, w = 2, 3, 7, 9, 70
+    ws = fc.fcfs_forward_3d_workspace(pd, phw, 0, n, c, d, h, w)
+    do, ho, wo = 3 * 4, 5 * 3, 2 * 24
+    assert ws == 4 * min(n * c * d * ho * wo, n * c * do * h * w)
+    assert fc.fcfs_forward_3d_workspace(pd, phw, 1, n, c, d, h, w) == ws // 2
+    assert fc.fcfs_forward_3d(pd, phw, 0, n, c, d, h, w, 16, 16, 16, ws - 1, None) == fc.E_INVAL
+    assert fc.fcfs_forward_3d(pd, phw, 0, n, c, d, h, w, None, 16, 16, ws, None) == fc.E_INVAL
+    assert fc.fcfs_forward_3d(pd, phw, 0, 0, c, d, h, w, None, None, None, 0, None) == fc.OK
+    # the depth plan's width must be 1/1; methods must agree; paper grid refused
+    assert fc.fcfs_forward_3d(phw, phw, 0, n, c, d, h, w, 16, 16, 16, 1 << 30, None) == fc.E_INVAL
+    other = fc.fcfs_plan_ex(3, 2, 1, 1, 1, 2, 0)
+    assert fc.fcfs_forward_3d(other, phw, 0, n, c, d, h, w, 16, 16, 16, 1 << 30, None) == fc.E_INVAL
+    pd_paper = fc.fcfs_plan_ex(3, 2, 1, 1, 2, 2, 1)
+    phw_paper = fc.fcfs_plan_ex(5, 4, 2, 3, 2, 2, 1)
+    assert fc.fcfs_forward_3d(pd_paper, phw_paper, 0, n, c, d, h, w, 16, 16, 16, 1 << 30, None) == fc.E_UNSUPPORTED
+    dw4 = fc.fcfs_plan_ex(3, 2, 1, 1, 3, 2, 0)
+    assert fc.fcfs_forward_3d(dw4, phw, 0, n, c, d, h, w, 16, 16, 16, 1 << 30, None) == fc.E_INVAL
+    for pl in (one, two, paper, pd, phw, other, pd_paper, phw_paper, dw4):
+        fc.fcfs_plan_destroy(pl)
