@@ -157,7 +157,30 @@ def measure_rows(reps: int):
     out["mix4_5_4_16x64x512_bf16"] = {"us": round(us, 2), "flop": flops,
                                       "TFLOPs": round(flops / us / 1e6, 1),
                                       "mfma_frac": round(flops / us / 1e6 / MFMA_PEAK_BF16_TFLOPS, 4)}
-    del xb, wm, ym
+    # its backward: input gradient (VALU gather) and weight gradient (MFMA), each
+    # the same flop count as the forward
+    dym = ym
+    dxm = torch.empty_like(xb)
+    dwm = torch.empty(wm.shape, dtype=torch.float32, device=dev)
+    wsb = fc.fcfs_backward_workspace(plm.handle, 1, N, C, H, W, C)
+    wsm = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+
+    def runbx(i=0):
+        st = fc.fcfs_backward(plm.handle, 1, N, C, H, W, None, wm.data_ptr(), C, dym.data_ptr(), dxm.data_ptr(),
+                              None, wsm.data_ptr(), wsb, sp)
+        assert st == 0
+
+    def runbw(i=0):
+        st = fc.fcfs_backward(plm.handle, 1, N, C, H, W, xb.data_ptr(), None, C, dym.data_ptr(), None,
+                              dwm.data_ptr(), wsm.data_ptr(), wsb, sp)
+        assert st == 0
+    ux = timeit(runbx, max(2, reps // 4))
+    uw = timeit(runbw, max(2, reps // 4))
+    out["mix4_5_4_16x64x512_bf16_backward"] = {
+        "dx_us": round(ux, 2), "dx_TFLOPs": round(flops / ux / 1e6, 1),
+        "dw_us": round(uw, 2), "dw_TFLOPs": round(flops / uw / 1e6, 1),
+        "dw_mfma_frac": round(flops / uw / 1e6 / MFMA_PEAK_BF16_TFLOPS, 4)}
+    del xb, wm, ym, dxm, dwm, wsm
     torch.cuda.empty_cache()
     # learned depthwise 8 x 64 x 256^2 at 3/4, forward and backward
     N, C, H, W, p, q = 8, 64, 256, 256, 3, 4

@@ -498,6 +498,8 @@ def _make_function():
             need_dw = w is not None and ctx.needs_input_grad[1]
             dx, dw = ctx.plan.backward(dy.contiguous(), ctx.x_shape, x=x if need_dw else None,
                                        weight=w, need_dx=need_dx, need_dw=need_dw)
+            if dw is not None and dw.dtype != w.dtype:
+                dw = dw.to(w.dtype)   # (the FP32 weight gradient, in the parameter's type)
             return dx, dw, None
 
     return FCFSFunction

@@ -161,10 +161,12 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Fills the size-dependent fields of the backward arguments and returns the
 // workspace layout: [height table][width table][weight-gradient partials].
-static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, int h, int w, int ho,
-                                 int wo, bool need_dw, BwdArgs* a, size_t* ws_bytes, size_t* off_w,
+static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, int64_t c_out, int h, int w,
+                                 int ho, int wo, bool need_dw, BwdArgs* a, size_t* ws_bytes, size_t* off_w,
                                  size_t* off_p) {
   a->planes = n * c;
+  a->planes_n = (int)n;
+  a->Cout = (int)c_out;
   a->C = (int)c;
   a->H = h;
   a->W = w;
@@ -183,6 +185,19 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
   *off_w = bytes;
   bytes += align256(sizeof(int) * (size_t)w * (3 + a->cmax_w));
   *off_p = bytes;
+  if (plan->method == FCFS_LEARNED_MIX4) {
+    // input gradient: 32 channels per workgroup; weight gradient: partial
+    // sums of up to 8 chunks of cell rows
+    a->mix_cblocks = (int)((c + 31) / 32);
+    a->mix_otiles = (int)((a->Cout + 31) / 32);
+    a->mix_ctiles = (int)((c + 7) / 8);
+    const int64_t rows = n * (int64_t)a->Mh;
+    a->mix_kchunks = (int)std::max<int64_t>(1, std::min<int64_t>(8, rows));
+    if (need_dw)
+      bytes += align256(sizeof(float) * (size_t)a->mix_kchunks * plan->ah.p * plan->aw.p * a->Cout * c * 16);
+    *ws_bytes = bytes;
+    return FCFS_OK;
+  }
   if (need_dw) {
     // chunks of ch x cw cells: staged x patch within 8192 floats
     const AxisTable &th = plan->ah, &tw = plan->aw;
@@ -576,9 +591,9 @@ static fcfs_status backward_checks(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n
                                    int64_t* wo) {
   fcfs_status st = check_common(plan, dtype, n, c_in, h, w, c_out, ho, wo);
   if (st != FCFS_OK) return st;
-  if (plan->method == FCFS_LEARNED_MIX4) return FCFS_E_UNSUPPORTED;
+  if (plan->method == FCFS_LEARNED_MIX4 && dtype == FCFS_F32) return FCFS_E_UNSUPPORTED;
   if (plan->method == FCFS_LEARNED_DW4 && plan->ah.p * plan->aw.p > 64) return FCFS_E_UNSUPPORTED;
-  if (need_dw && plan->method != FCFS_LEARNED_DW4) return FCFS_E_INVAL;
+  if (need_dw && plan->method != FCFS_LEARNED_DW4 && plan->method != FCFS_LEARNED_MIX4) return FCFS_E_INVAL;
   if (*ho >= (1 << 24) || *wo >= (1 << 24)) return FCFS_E_UNSUPPORTED;   // adjoint table entries pack k < 2^24
   return FCFS_OK;
 }
@@ -588,7 +603,7 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
   int64_t ho = 0, wo = 0;
   if (!bytes) return FCFS_E_INVAL;
   *bytes = 0;
-  const bool learned = plan && plan->method == FCFS_LEARNED_DW4;
+  const bool learned = plan && (plan->method == FCFS_LEARNED_DW4 || plan->method == FCFS_LEARNED_MIX4);
   fcfs_status st = backward_checks(plan, dtype, n, c_in, h, w, c_out, false, &ho, &wo);
   if (st != FCFS_OK) return st;
   if (n == 0 || c_in == 0 || h == 0 || w == 0) return FCFS_OK;
@@ -596,7 +611,7 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
   std::memset(&a, 0, sizeof(a));
   size_t off_w, off_p;
   // sized for the weight gradient too when the method has weights
-  return plan_backward(plan, n, c_in, (int)h, (int)w, (int)ho, (int)wo, learned, &a, bytes, &off_w, &off_p);
+  return plan_backward(plan, n, c_in, c_out, (int)h, (int)w, (int)ho, (int)wo, learned, &a, bytes, &off_w, &off_p);
 }
 
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
@@ -606,13 +621,13 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
   int64_t ho = 0, wo = 0;
   fcfs_status st = backward_checks(plan, dtype, n, c_in, h, w, c_out, dw != nullptr, &ho, &wo);
   if (st != FCFS_OK) return st;
-  const bool learned = plan->method == FCFS_LEARNED_DW4;
+  const bool mix = plan->method == FCFS_LEARNED_MIX4;
+  const bool learned = plan->method == FCFS_LEARNED_DW4 || mix;
   if (n == 0 || c_in == 0 || h == 0 || w == 0) {
     // no samples: the weight gradient is an empty sum
     if (dw) {
-      if (hipMemsetAsync(dw, 0, sizeof(float) * (size_t)c_in * plan->ah.p * plan->aw.p * 16, stream) !=
-          hipSuccess)
-        return FCFS_E_DEVICE;
+      const size_t count = (size_t)c_in * (mix ? c_out : 1) * plan->ah.p * plan->aw.p * 16;
+      if (hipMemsetAsync(dw, 0, sizeof(float) * count, stream) != hipSuccess) return FCFS_E_DEVICE;
     }
     return FCFS_OK;
   }
@@ -624,7 +639,9 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
   BwdArgs a;
   std::memset(&a, 0, sizeof(a));
   size_t need = 0, off_w = 0, off_p = 0;
-  st = plan_backward(plan, n, c_in, (int)h, (int)w, (int)ho, (int)wo, dw != nullptr, &a, &need, &off_w, &off_p);
+  if (mix && dx && (reinterpret_cast<uintptr_t>(weight) & 15) != 0) return FCFS_E_INVAL;
+  st = plan_backward(plan, n, c_in, c_out, (int)h, (int)w, (int)ho, (int)wo, dw != nullptr, &a, &need, &off_w,
+                     &off_p);
   if (st != FCFS_OK) return st;
   if (!workspace || ws_bytes < need) return FCFS_E_INVAL;
   char* ws = static_cast<char*>(workspace);
@@ -636,6 +653,11 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
   a.tab_h = reinterpret_cast<int*>(ws);
   a.tab_w = reinterpret_cast<int*>(ws + off_w);
   a.partial = dw ? reinterpret_cast<float*>(ws + off_p) : nullptr;
+  if (mix) {
+    a.weight = nullptr;
+    a.mix_weight = weight;
+    return dtype == FCFS_BF16 ? launch_backward_mix_bf16(a, stream) : launch_backward_mix_f16(a, stream);
+  }
   switch (dtype) {
     case FCFS_F32: return launch_backward_f32(a, learned, stream);
     case FCFS_BF16: return launch_backward_bf16(a, learned, stream);

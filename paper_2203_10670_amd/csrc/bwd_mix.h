@@ -1,0 +1,265 @@
+// Backward of the channel-mixing FCFS layer (Sec. 7's learnable weights with
+// channel mixing) for gfx950, 16-bit storage with FP32 accumulation.
+//
+// Forward: y[n][o][p*mh + jh][p*mw + jw] = sum over c, a, b of
+//   W[jh][jw][o][c][a][b] * ext(x)[n][c][q*mh + off_h(jh) + a][q*mw + off_w(jw) + b].
+//
+// Input gradient (dx_mix_kernel): the adjoint, gathered per input sample from
+// the adjoint tables of bwd_kernel.h (entries (k, j, tap) per input index,
+// with the padding folded in):
+//   dx[n][c][i][j] = sum over height entries (kh, jh, a), width entries
+//   (kw, jw, b) and outputs o of W[jh][jw][o][c][a][b] * dy[n][o][kh][kw].
+// A workgroup takes 256 columns of one input row and 32 input channels, one
+// column per thread and the 32 channels in registers. The row's height
+// entries are the same for every thread, so for each (height entry, chunk of
+// 8 outputs) the weights of every width phase and tap are staged in LDS as
+// [jw][b][o][c] and each thread adds, for each of its width entries and each
+// output, one dy sample times 32 weights (8 broadcast 16-byte reads). Every
+// sum runs in a fixed order; there are no atomics.
+//
+// Weight gradient (dw_mix_partial_kernel, dw_mix_reduce_kernel): for each
+// phase a GEMM over cells, dW[o][(c, a, b)] = sum over cells of
+// dy[cell][o] * ext(x)[cell's tap (a, b)][c], on MFMA 16x16x32 with the cells
+// as the reduction: a workgroup takes one phase, 32 outputs, 8 input channels
+// (128 columns (c, a, b)) and a chunk of cell rows; each wave stages its own
+// cell rows (no barriers), 32 cells at a time, as [o][cell] and
+// [(c, a, b)][cell] in LDS so that both fragments are 16-byte reads, and
+// accumulates 2 x 8 tiles. The waves' tiles are added in a fixed order, and
+// the chunks in a second kernel, in order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bwd_kernel.h"
+#include "fcfs_internal.h"
+#include "fwd_kernel.h"
+#include "mix4_kernel.h"
+
+namespace fcfs {
+namespace bwdmix {
+
+using fwd::pad_source;
+using fwd::Store;
+using mix::f32x4;
+using mix::Mfma;
+using mix::u16x8;
+
+constexpr int kThreads = 256;
+constexpr int kDxChannels = 32;   // input channels per input-gradient workgroup
+constexpr int kDxOuts = 8;        // outputs per staged weight slice
+
+template <int DT>
+__global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
+  using S = Store<DT>;
+  using TS = typename S::T;
+  extern __shared__ float smem[];   // [p_w][4][kDxOuts][kDxChannels]
+  const AxisTable& TW = a.tw_tab;
+  int64_t blk = blockIdx.x;
+  const int cblk = (int)(blk % a.mix_cblocks); blk /= a.mix_cblocks;
+  const int colb = (int)(blk % a.col_blocks); blk /= a.col_blocks;
+  const int i = (int)(blk % a.H);
+  const int n = (int)(blk / a.H);
+  const int c0 = cblk * kDxChannels;
+  const int j = colb * kThreads + threadIdx.x;
+  const bool live = j < a.W;
+  const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
+  const int* rw = a.tab_w + (int64_t)(live ? j : 0) * (3 + a.cmax_w);
+  const int nh = rh[0], nw = live ? rw[0] : 0;
+  const uint16_t* wt = reinterpret_cast<const uint16_t*>(a.mix_weight);
+  const TS* dyn = reinterpret_cast<const TS*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo;
+  const int64_t oplane = (int64_t)a.Ho * a.Wo;
+  float acc[kDxChannels];
+#pragma unroll
+  for (int c = 0; c < kDxChannels; ++c) acc[c] = 0.f;
+
+  for (int o0 = 0; o0 < a.Cout; o0 += kDxOuts) {
+    for (int eh = 0; eh < nh; ++eh) {
+      const int ent = rh[3 + eh];
+      const int kh = ent >> 7, jh = (ent >> 2) & 31, ta = ent & 3;
+      __syncthreads();   // the previous slice is consumed
+      // stage W[jh][jw][o0 + o][c0 + c][ta][0..3] for every jw, o, c
+      for (int it = threadIdx.x; it < TW.p * kDxOuts * kDxChannels; it += kThreads) {
+        const int c = it % kDxChannels, o = (it / kDxChannels) % kDxOuts, jw = it / (kDxChannels * kDxOuts);
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (o0 + o < a.Cout && c0 + c < a.C) {
+          const uint16_t* src =
+              wt + ((((int64_t)jh * TW.p + jw) * a.Cout + o0 + o) * a.C + c0 + c) * 16 + ta * 4;
+          const uint2 raw = *reinterpret_cast<const uint2*>(src);   // 4 taps, 8-byte aligned
+          v[0] = S::from_bits(raw.x & 0xffffu);
+          v[1] = S::from_bits(raw.x >> 16);
+          v[2] = S::from_bits(raw.y & 0xffffu);
+          v[3] = S::from_bits(raw.y >> 16);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) smem[((jw * 4 + b) * kDxOuts + o) * kDxChannels + c] = v[b];
+      }
+      __syncthreads();
+      const TS* dyr = dyn + (int64_t)o0 * oplane + (int64_t)kh * a.Wo;
+      for (int ew = 0; ew < nw; ++ew) {
+        const int went = rw[3 + ew];
+        const int kw = went >> 7, jw = (went >> 2) & 31, tb = went & 3;
+        const float* ws = smem + (jw * 4 + tb) * kDxOuts * kDxChannels;
+        float dv[kDxOuts];
+#pragma unroll
+        for (int o = 0; o < kDxOuts; ++o) dv[o] = (o0 + o < a.Cout) ? S::load(dyr + o * oplane + kw) : 0.f;
+#pragma unroll
+        for (int o = 0; o < kDxOuts; ++o) {
+          const float4* w4 = reinterpret_cast<const float4*>(ws + o * kDxChannels);
+#pragma unroll
+          for (int q4 = 0; q4 < kDxChannels / 4; ++q4) {
+            const float4 w = w4[q4];
+            acc[4 * q4 + 0] = __builtin_fmaf(w.x, dv[o], acc[4 * q4 + 0]);
+            acc[4 * q4 + 1] = __builtin_fmaf(w.y, dv[o], acc[4 * q4 + 1]);
+            acc[4 * q4 + 2] = __builtin_fmaf(w.z, dv[o], acc[4 * q4 + 2]);
+            acc[4 * q4 + 3] = __builtin_fmaf(w.w, dv[o], acc[4 * q4 + 3]);
+          }
+        }
+      }
+    }
+  }
+  if (!live) return;
+  TS* dxp = reinterpret_cast<TS*>(a.dx) + ((int64_t)n * a.C * a.H + i) * a.W + j;
+#pragma unroll
+  for (int c = 0; c < kDxChannels; ++c)
+    if (c0 + c < a.C) S::store(dxp + (int64_t)(c0 + c) * a.H * a.W, acc[c]);
+}
+
+constexpr int kDwOuts = 32;   // outputs per weight-gradient workgroup (2 M tiles)
+constexpr int kDwChan = 8;    // input channels per workgroup: 8 x 16 taps = 128 columns (8 N tiles)
+constexpr int kDwCells = 32;  // cells per MFMA reduction step
+
+// Partial sums of one chunk of cell rows: partial[chunk][phase][o][c][16].
+template <int DT>
+__global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs a) {
+  using M = Mfma<DT>;
+  extern __shared__ float smem[];
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+  int64_t blk = blockIdx.x;
+  const int chunk = (int)(blk % a.mix_kchunks); blk /= a.mix_kchunks;
+  const int ctile = (int)(blk % a.mix_ctiles); blk /= a.mix_ctiles;
+  const int otile = (int)(blk % a.mix_otiles); blk /= a.mix_otiles;
+  const int ph = (int)blk;
+  const int jh = ph / TW.p, jw = ph % TW.p;
+  const int o0 = otile * kDwOuts, c0 = ctile * kDwChan;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, g4 = lane >> 4;
+  // wave-private staging: A [32 o][32 cells], B [128 (c, a, b)][32 cells] (16-bit)
+  uint16_t* const As = reinterpret_cast<uint16_t*>(smem) + wave * (kDwOuts + 16 * kDwChan) * kDwCells;
+  uint16_t* const Bs = As + kDwOuts * kDwCells;
+  const int G = a.planes_n * a.Mh;   // cell rows (n, mh)
+  const int g_lo = (int)((int64_t)G * chunk / a.mix_kchunks);
+  const int g_hi = (int)((int64_t)G * (chunk + 1) / a.mix_kchunks);
+  // both operands move as raw 16-bit samples
+  const uint16_t* dyb = reinterpret_cast<const uint16_t*>(a.dy);
+  const uint16_t* xb = reinterpret_cast<const uint16_t*>(a.x);
+  const int64_t oplane = (int64_t)a.Ho * a.Wo, iplane = (int64_t)a.H * a.W;
+
+  f32x4 acc[2][8];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int g = g_lo + wave; g < g_hi; g += 4) {
+    const int n = g / a.Mh, mh = g % a.Mh;
+    const int orow = TH.p * mh + jh;
+    // source rows of the 4 tap rows (-1: zero padding)
+    int srow[4];
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta) srow[ta] = pad_source(TH.q * mh + TH.off[jh] + ta, a.H, a.pad);
+    for (int mw0 = 0; mw0 < a.Mw; mw0 += kDwCells) {
+      // A: dy[n][o0 + o][orow][p (mw0 + k) + jw], element e = lane + 64 t: o = e / 32, k = e % 32
+#pragma unroll
+      for (int t = 0; t < kDwOuts * kDwCells / 64; ++t) {
+        const int e = lane + 64 * t, o = e >> 5, k = e & 31;
+        const bool ok = o0 + o < a.Cout && mw0 + k < a.Mw;
+        const uint16_t* src = dyb + ((int64_t)n * a.Cout + (ok ? o0 + o : 0)) * oplane + (int64_t)orow * a.Wo +
+                              (ok ? TW.p * (mw0 + k) + jw : 0);
+        As[o * kDwCells + k] = ok ? *src : (uint16_t)0;
+      }
+      // B: ext(x)[n][c0 + c][row of ta][q (mw0 + k) + off_w(jw) + tb], column (c, ta, tb)
+#pragma unroll 4
+      for (int t = 0; t < 16 * kDwChan * kDwCells / 64; ++t) {
+        const int e = lane + 64 * t, k = e & 31, col = e >> 5;
+        const int c = col >> 4, ta = (col >> 2) & 3, tb = col & 3;
+        const int sc = pad_source(TW.q * (mw0 + k) + TW.off[jw] + tb, a.W, a.pad);
+        const int sr = srow[ta];
+        const bool ok = c0 + c < a.C && mw0 + k < a.Mw && sr >= 0 && sc >= 0;
+        const uint16_t* src = xb + ((int64_t)n * a.C + (ok ? c0 + c : 0)) * iplane + (ok ? (int64_t)sr * a.W + sc : 0);
+        Bs[col * kDwCells + k] = ok ? *src : (uint16_t)0;
+      }
+      fwd::wave_lds_sync();
+      u16x8 af[2], bf[8];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) af[mt] = *reinterpret_cast<const u16x8*>(As + (mt * 16 + li) * kDwCells + 8 * g4);
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt) bf[nt] = *reinterpret_cast<const u16x8*>(Bs + (nt * 16 + li) * kDwCells + 8 * g4);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+      fwd::wave_lds_sync();
+    }
+  }
+  // add the 4 waves' tiles in order (wave 0 first) through LDS, then write
+  // partial[chunk][ph][o][c][tap]
+  __syncthreads();
+  float* red = smem;   // [4 waves][32 o][128 cols]
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = mt * 16 + 4 * g4 + r, col = nt * 16 + li;   // D: col l%16, rows 4(l/16)+r
+        red[(wave * kDwOuts + o) * 128 + col] = acc[mt][nt][r];
+      }
+  __syncthreads();
+  float* out = a.partial + (((int64_t)chunk * TH.p * TW.p + ph) * a.Cout) * a.C * 16;
+  for (int e = threadIdx.x; e < kDwOuts * 128; e += kThreads) {
+    const int o = e / 128, col = e % 128, c = col >> 4, tap = col & 15;
+    if (o0 + o >= a.Cout || c0 + c >= a.C) continue;
+    float s = red[o * 128 + col];
+    for (int w = 1; w < 4; ++w) s += red[(w * kDwOuts + o) * 128 + col];
+    out[((int64_t)(o0 + o) * a.C + c0 + c) * 16 + tap] = s;
+  }
+}
+
+// dw[ph][o][c][tap] = sum of the chunks' partials, in chunk order.
+__global__ __launch_bounds__(kThreads) void dw_mix_reduce_kernel(const BwdArgs a) {
+  const int64_t per = (int64_t)a.th.p * a.tw_tab.p * a.Cout * a.C * 16;
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= per) return;
+  float s = 0.f;
+  for (int k = 0; k < a.mix_kchunks; ++k) s += a.partial[k * per + e];
+  a.dw[e] = s;
+}
+
+template <int DT>
+fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
+  const dim3 block(kThreads);
+  hipLaunchKernelGGL((bwd::adjoint_tables_kernel<DT>), dim3((unsigned)(((int64_t)a.H + a.W + kThreads - 1) / kThreads)),
+                     block, 0, stream, a);
+  if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  if (a.dx) {
+    const int64_t blocks = (int64_t)a.planes_n * a.H * a.col_blocks * a.mix_cblocks;
+    const size_t lds = sizeof(float) * a.tw_tab.p * 4 * kDxOuts * kDxChannels;
+    hipLaunchKernelGGL((dx_mix_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  }
+  if (a.dw) {
+    const int64_t blocks = (int64_t)a.th.p * a.tw_tab.p * a.mix_otiles * a.mix_ctiles * a.mix_kchunks;
+    const size_t lds = sizeof(float) * 4 * kDwOuts * 128;   // >= the staging (4 x 10 KB)
+    hipLaunchKernelGGL((dw_mix_partial_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+    const int64_t per = (int64_t)a.th.p * a.tw_tab.p * a.Cout * a.C * 16;
+    hipLaunchKernelGGL((dw_mix_reduce_kernel), dim3((unsigned)((per + kThreads - 1) / kThreads)), block, 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  }
+  return FCFS_OK;
+}
+
+}  // namespace bwdmix
+}  // namespace fcfs

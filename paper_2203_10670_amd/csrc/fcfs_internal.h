@@ -96,6 +96,12 @@ struct BwdArgs {
   int ch, cw, nch, ncw;  // weight-gradient chunk: ch x cw cells, nch x ncw chunks per plane
   int chunks_per_channel;
   int dw_lds_bytes;
+  // channel-mixing layer
+  int planes_n;            // batch
+  int Cout;                // output channels (C = input channels)
+  const void* mix_weight;  // [p_h][p_w][Cout][C][4][4], 16-bit storage
+  int mix_cblocks;         // input-gradient workgroups per row block: ceil(C / 32)
+  int mix_otiles, mix_ctiles, mix_kchunks;   // weight gradient: 32 outputs x 8 channels x chunks of cell rows
   AxisTable th, tw_tab;
 };
 
@@ -171,6 +177,8 @@ fcfs_status launch_mix4(int dtype, const MixArgs& a, hipStream_t stream);
 fcfs_status launch_backward_f32(const BwdArgs& a, bool learned, hipStream_t stream);
 fcfs_status launch_backward_bf16(const BwdArgs& a, bool learned, hipStream_t stream);
 fcfs_status launch_backward_f16(const BwdArgs& a, bool learned, hipStream_t stream);
+fcfs_status launch_backward_mix_bf16(const BwdArgs& a, hipStream_t stream);
+fcfs_status launch_backward_mix_f16(const BwdArgs& a, hipStream_t stream);
 
 // Forward kernel launchers, one per storage type (fwd_<dtype>.hip).
 fcfs_status launch_forward_f32(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);

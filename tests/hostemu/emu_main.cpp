@@ -12,9 +12,12 @@ alignas(16) float smem[hostemu::kLdsFloats];
 namespace mix {
 alignas(16) float smem[hostemu::kLdsFloats];
 }  // namespace mix
+namespace bwdmix {
+alignas(16) float smem[hostemu::kLdsFloats];
+}  // namespace bwdmix
 }  // namespace fcfs
 
 namespace hostemu {
-float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem, fcfs::mix::smem};
+float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem, fcfs::mix::smem, fcfs::bwdmix::smem};
 const int n_lds_arrays = sizeof(lds_arrays) / sizeof(lds_arrays[0]);
 }  // namespace hostemu

@@ -102,6 +102,12 @@ typedef hostemu::BufferRsrc __amdgpu_buffer_rsrc_t;
 struct uint4 {
   unsigned x, y, z, w;
 };
+struct uint2 {
+  unsigned x, y;
+};
+struct float4 {
+  float x, y, z, w;
+};
 
 #ifndef __clang__
 // IEEE binary16 storage with round-to-nearest-even conversion from float

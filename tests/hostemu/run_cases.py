@@ -42,16 +42,19 @@ def from_storage(y, dt):
     return y.astype(np.float32)
 
 
-def run_backward(lib, plan, c, i, xs, xv, w, N, C, H, W, Ho, Wo, p, q, pw, qw, m, pad, grid, dt):
-    dyv = synth.normal(3000 + i, (N, C, Ho, Wo))
+def run_backward(lib, plan, c, i, xs, xv, w, N, C, H, W, Ho, Wo, p, q, pw, qw, m, pad, grid, dt, wptr=None, Co=None):
+    Co = C if Co is None else Co
+    dyv = synth.normal(3000 + i, (N, Co, Ho, Wo))
     dys, dyv = to_storage(dyv, dt)
-    need_dw = m == "dw4"
+    need_dw = m in ("dw4", "mix4")
     ws = ctypes.c_size_t()
-    assert lib.fcfs_backward_workspace(plan, DT[dt], N, C, H, W, C, ctypes.byref(ws)) == 0
+    assert lib.fcfs_backward_workspace(plan, DT[dt], N, C, H, W, Co, ctypes.byref(ws)) == 0
     wsb = np.zeros(max(1, ws.value) // 4 + 64, dtype=np.int32)
     dx = np.zeros((N, C, H, W), dtype=xs.dtype)
-    dw = np.zeros_like(w) if need_dw else None
-    st = lib.fcfs_backward(plan, DT[dt], N, C, H, W, xs.ctypes.data, None if w is None else w.ctypes.data, C,
+    dw = np.zeros(w.shape, dtype=np.float32) if need_dw else None
+    if wptr is None and w is not None:
+        wptr = w.ctypes.data
+    st = lib.fcfs_backward(plan, DT[dt], N, C, H, W, xs.ctypes.data, wptr, Co,
                            dys.ctypes.data, dx.ctypes.data, None if dw is None else dw.ctypes.data,
                            wsb.ctypes.data, ws.value, None)
     assert st == 0, st
@@ -110,7 +113,7 @@ def main():
             wptr = wbits.ctypes.data
         if c.get("mode") == "bwd":
             ok = run_backward(lib, plan, c, i, xs, xv, w, N, C, H, W, ho.value, wo.value, p, q, pw, qw, m, pad,
-                              grid, dt)
+                              grid, dt, wptr=wptr, Co=Co)
             print("case", i, json.dumps(c), "ok" if ok else "MISMATCH", flush=True)
             if not ok:
                 sys.exit(1)

@@ -85,6 +85,19 @@ def test_copy_axis_beside_resampled_axis():
     _run(cases)
 
 
+def test_channel_mixing_backward():
+    # input gradient (gathered over the adjoint tables) and weight gradient
+    # (MFMA over cells, chunks added in order), 16-bit storage
+    cases = []
+    for (p, q, pad, dt, shape, cout) in [(5, 4, "reflect", "bf16", [2, 3, 9, 40], 5),
+                                          (3, 2, "zero", "f16", [1, 9, 7, 35], 33),
+                                          (2, 3, "replicate", "bf16", [1, 2, 11, 300], 3),
+                                          (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2)]:
+        cases.append({"mode": "bwd", "p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": shape,
+                      "cout": cout})
+    _run(cases)
+
+
 def test_grids_anisotropic_degenerate():
     _run([{"p": 3, "q": 2, "pw": 4, "qw": 5, "method": "bicubic", "pad": "zero", "shape": [1, 1, 19, 80]},
           {"p": 3, "q": 2, "method": "bilinear", "pad": "reflect", "grid": "paper", "shape": [1, 1, 12, 40]},
