@@ -47,12 +47,16 @@ using mix::u16x8;
 constexpr int kThreads = 256;
 constexpr int kDxChannels = 32;   // input channels per input-gradient workgroup
 constexpr int kDxOuts = 8;        // outputs per staged weight slice
+// One (jw, b) block of the slice is kDxOuts x kDxChannels floats (1 KB); the
+// blocks sit 1 KB + 16 B apart, so that the lanes of a half-wave, which read
+// from up to p_w * 4 blocks, hit different LDS banks.
+constexpr int kDxBlock = kDxOuts * kDxChannels + 4;
 
 template <int DT>
 __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
   using S = Store<DT>;
   using TS = typename S::T;
-  extern __shared__ float smem[];   // [p_w][4][kDxOuts][kDxChannels]
+  extern __shared__ float smem[];   // [p_w * 4 blocks of kDxBlock][kDxOuts][kDxChannels]
   const AxisTable& TW = a.tw_tab;
   int64_t blk = blockIdx.x;
   const int cblk = (int)(blk % a.mix_cblocks); blk /= a.mix_cblocks;
@@ -91,14 +95,14 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
           v[3] = S::from_bits(raw.y >> 16);
         }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) smem[((jw * 4 + b) * kDxOuts + o) * kDxChannels + c] = v[b];
+        for (int b = 0; b < 4; ++b) smem[(jw * 4 + b) * kDxBlock + o * kDxChannels + c] = v[b];
       }
       __syncthreads();
       const TS* dyr = dyn + (int64_t)o0 * oplane + (int64_t)kh * a.Wo;
       for (int ew = 0; ew < nw; ++ew) {
         const int went = rw[3 + ew];
         const int kw = went >> 7, jw = (went >> 2) & 31, tb = went & 3;
-        const float* ws = smem + (jw * 4 + tb) * kDxOuts * kDxChannels;
+        const float* ws = smem + (jw * 4 + tb) * kDxBlock;
         float dv[kDxOuts];
 #pragma unroll
         for (int o = 0; o < kDxOuts; ++o) dv[o] = (o0 + o < a.Cout) ? S::load(dyr + o * oplane + kw) : 0.f;
@@ -162,46 +166,78 @@ __global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs 
 #pragma unroll
     for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int g = g_lo + wave; g < g_hi; g += 4) {
+  // A staging: lane -> cells 2 k2, 2 k2 + 1 and outputs (lane >> 4) + 4 t, t < 8.
+  // B staging: lane -> the same cells and columns (c, ta, tb) = (t >> 2,
+  // t & 3, lane >> 4), t < 32 (16-bit samples in 32-bit registers, packed in
+  // pairs of cells when stored).
+  const int k2 = lane & 15, hi = lane >> 4;
+  const int tb = hi;
+  uint32_t pa[8][2], pb[32][2];
+  // the K steps of this wave: (cell row g, 32 cells from mw0)
+  const int nks = (a.Mw + kDwCells - 1) / kDwCells;
+  auto load_step = [&](int g, int mw0) __attribute__((always_inline)) {
     const int n = g / a.Mh, mh = g % a.Mh;
     const int orow = TH.p * mh + jh;
-    // source rows of the 4 tap rows (-1: zero padding)
     int srow[4];
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta) srow[ta] = pad_source(TH.q * mh + TH.off[jh] + ta, a.H, a.pad);
-    for (int mw0 = 0; mw0 < a.Mw; mw0 += kDwCells) {
-      // A: dy[n][o0 + o][orow][p (mw0 + k) + jw], element e = lane + 64 t: o = e / 32, k = e % 32
+    int sc[2];
+    bool kok[2];
 #pragma unroll
-      for (int t = 0; t < kDwOuts * kDwCells / 64; ++t) {
-        const int e = lane + 64 * t, o = e >> 5, k = e & 31;
-        const bool ok = o0 + o < a.Cout && mw0 + k < a.Mw;
-        const uint16_t* src = dyb + ((int64_t)n * a.Cout + (ok ? o0 + o : 0)) * oplane + (int64_t)orow * a.Wo +
-                              (ok ? TW.p * (mw0 + k) + jw : 0);
-        As[o * kDwCells + k] = ok ? *src : (uint16_t)0;
-      }
-      // B: ext(x)[n][c0 + c][row of ta][q (mw0 + k) + off_w(jw) + tb], column (c, ta, tb)
-#pragma unroll 4
-      for (int t = 0; t < 16 * kDwChan * kDwCells / 64; ++t) {
-        const int e = lane + 64 * t, k = e & 31, col = e >> 5;
-        const int c = col >> 4, ta = (col >> 2) & 3, tb = col & 3;
-        const int sc = pad_source(TW.q * (mw0 + k) + TW.off[jw] + tb, a.W, a.pad);
-        const int sr = srow[ta];
-        const bool ok = c0 + c < a.C && mw0 + k < a.Mw && sr >= 0 && sc >= 0;
-        const uint16_t* src = xb + ((int64_t)n * a.C + (ok ? c0 + c : 0)) * iplane + (ok ? (int64_t)sr * a.W + sc : 0);
-        Bs[col * kDwCells + k] = ok ? *src : (uint16_t)0;
-      }
-      fwd::wave_lds_sync();
-      u16x8 af[2], bf[8];
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt) af[mt] = *reinterpret_cast<const u16x8*>(As + (mt * 16 + li) * kDwCells + 8 * g4);
-#pragma unroll
-      for (int nt = 0; nt < 8; ++nt) bf[nt] = *reinterpret_cast<const u16x8*>(Bs + (nt * 16 + li) * kDwCells + 8 * g4);
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
-      fwd::wave_lds_sync();
+    for (int e = 0; e < 2; ++e) {
+      const int mw = mw0 + 2 * k2 + e;
+      kok[e] = mw < a.Mw;
+      sc[e] = pad_source(TW.q * (kok[e] ? mw : 0) + TW.off[jw] + tb, a.W, a.pad);
     }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int o = hi + 4 * t;
+      const bool ook = o0 + o < a.Cout;
+      const uint16_t* row = dyb + ((int64_t)n * a.Cout + (ook ? o0 + o : 0)) * oplane + (int64_t)orow * a.Wo + jw;
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        pa[t][e] = (ook && kok[e]) ? row[TW.p * (mw0 + 2 * k2 + e)] : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int c = t >> 2, ta = t & 3;
+      const bool cok = c0 + c < a.C && srow[ta] >= 0;
+      const uint16_t* row = xb + ((int64_t)n * a.C + (cok ? c0 + c : 0)) * iplane + (int64_t)(cok ? srow[ta] : 0) * a.W;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) pb[t][e] = (cok && kok[e] && sc[e] >= 0) ? row[sc[e]] : 0u;
+    }
+  };
+  auto store_step = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      *reinterpret_cast<uint32_t*>(As + (hi + 4 * t) * kDwCells + 2 * k2) = pa[t][0] | (pa[t][1] << 16);
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int col = (t >> 2) * 16 + (t & 3) * 4 + tb;
+      *reinterpret_cast<uint32_t*>(Bs + col * kDwCells + 2 * k2) = pb[t][0] | (pb[t][1] << 16);
+    }
+  };
+  // this wave's steps: cell rows g_lo + wave, + 4, ...; 32-cell steps within each
+  const int rows_w = g_hi - g_lo > wave ? (g_hi - g_lo - wave + 3) / 4 : 0;
+  const int nsteps = rows_w * nks;
+  if (nsteps > 0) load_step(g_lo + wave, 0);
+  for (int s = 0; s < nsteps; ++s) {
+    store_step();
+    fwd::wave_lds_sync();
+    if (s + 1 < nsteps) {
+      const int s1 = s + 1;
+      load_step(g_lo + wave + 4 * (s1 / nks), (s1 % nks) * kDwCells);
+    }
+    u16x8 af[2], bf[8];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) af[mt] = *reinterpret_cast<const u16x8*>(As + (mt * 16 + li) * kDwCells + 8 * g4);
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) bf[nt] = *reinterpret_cast<const u16x8*>(Bs + (nt * 16 + li) * kDwCells + 8 * g4);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+    fwd::wave_lds_sync();
   }
   // add the 4 waves' tiles in order (wave 0 first) through LDS, then write
   // partial[chunk][ph][o][c][tap]
@@ -245,7 +281,7 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   if (a.dx) {
     const int64_t blocks = (int64_t)a.planes_n * a.H * a.col_blocks * a.mix_cblocks;
-    const size_t lds = sizeof(float) * a.tw_tab.p * 4 * kDxOuts * kDxChannels;
+    const size_t lds = sizeof(float) * a.tw_tab.p * 4 * kDxBlock;
     hipLaunchKernelGGL((dx_mix_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }
