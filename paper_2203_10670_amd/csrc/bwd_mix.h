@@ -175,46 +175,59 @@ __global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs 
   uint32_t pa[8][2], pb[32][2];
   // the K steps of this wave: (cell row g, 32 cells from mw0)
   const int nks = (a.Mw + kDwCells - 1) / kDwCells;
+  // Loads are unconditional, from clamped (valid) addresses; their masks are
+  // kept and applied when the step is stored, so nothing waits on a load
+  // before the step's MFMAs. Row bases of x are the same for the whole wave.
+  bool okA[2], okB[2];
+  uint32_t rowmask = 0;   // bit ta: tap row ta of this step is not zero padding
   auto load_step = [&](int g, int mw0) __attribute__((always_inline)) {
     const int n = g / a.Mh, mh = g % a.Mh;
     const int orow = TH.p * mh + jh;
-    int srow[4];
-#pragma unroll
-    for (int ta = 0; ta < 4; ++ta) srow[ta] = pad_source(TH.q * mh + TH.off[jh] + ta, a.H, a.pad);
-    int sc[2];
-    bool kok[2];
+    int colA[2], colB[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int mw = mw0 + 2 * k2 + e;
-      kok[e] = mw < a.Mw;
-      sc[e] = pad_source(TW.q * (kok[e] ? mw : 0) + TW.off[jw] + tb, a.W, a.pad);
+      const bool kok = mw < a.Mw;
+      colA[e] = TW.p * (kok ? mw : 0) + jw;
+      okA[e] = kok;
+      const int sc = pad_source(TW.q * (kok ? mw : 0) + TW.off[jw] + tb, a.W, a.pad);
+      colB[e] = sc >= 0 ? sc : 0;
+      okB[e] = kok && sc >= 0;
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int o = hi + 4 * t;
-      const bool ook = o0 + o < a.Cout;
-      const uint16_t* row = dyb + ((int64_t)n * a.Cout + (ook ? o0 + o : 0)) * oplane + (int64_t)orow * a.Wo + jw;
+      const uint16_t* row = dyb + ((int64_t)n * a.Cout + min(o0 + o, a.Cout - 1)) * oplane + (int64_t)orow * a.Wo;
 #pragma unroll
-      for (int e = 0; e < 2; ++e)
-        pa[t][e] = (ook && kok[e]) ? row[TW.p * (mw0 + 2 * k2 + e)] : 0u;
+      for (int e = 0; e < 2; ++e) pa[t][e] = row[colA[e]];
     }
+    rowmask = 0;
 #pragma unroll
-    for (int t = 0; t < 32; ++t) {
-      const int c = t >> 2, ta = t & 3;
-      const bool cok = c0 + c < a.C && srow[ta] >= 0;
-      const uint16_t* row = xb + ((int64_t)n * a.C + (cok ? c0 + c : 0)) * iplane + (int64_t)(cok ? srow[ta] : 0) * a.W;
+    for (int ta = 0; ta < 4; ++ta) {
+      const int sr = pad_source(TH.q * mh + TH.off[jh] + ta, a.H, a.pad);
+      rowmask |= (sr >= 0 ? 1u : 0u) << ta;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) pb[t][e] = (cok && kok[e] && sc[e] >= 0) ? row[sc[e]] : 0u;
+      for (int c = 0; c < kDwChan; ++c) {
+        const uint16_t* row = xb + ((int64_t)n * a.C + min(c0 + c, a.C - 1)) * iplane + (int64_t)(sr >= 0 ? sr : 0) * a.W;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) pb[c * 4 + ta][e] = row[colB[e]];
+      }
     }
   };
   auto store_step = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-      *reinterpret_cast<uint32_t*>(As + (hi + 4 * t) * kDwCells + 2 * k2) = pa[t][0] | (pa[t][1] << 16);
+    for (int t = 0; t < 8; ++t) {
+      const bool ook = o0 + hi + 4 * t < a.Cout;
+      const uint32_t lo = (ook && okA[0]) ? pa[t][0] : 0u, hi16 = (ook && okA[1]) ? pa[t][1] : 0u;
+      *reinterpret_cast<uint32_t*>(As + (hi + 4 * t) * kDwCells + 2 * k2) = lo | (hi16 << 16);
+    }
 #pragma unroll
     for (int t = 0; t < 32; ++t) {
-      const int col = (t >> 2) * 16 + (t & 3) * 4 + tb;
-      *reinterpret_cast<uint32_t*>(Bs + col * kDwCells + 2 * k2) = pb[t][0] | (pb[t][1] << 16);
+      const int c = t >> 2, ta = t & 3;
+      const bool cok = ((rowmask >> ta) & 1u) && c0 + c < a.C;
+      const uint32_t lo = (cok && okB[0]) ? pb[t][0] : 0u, hi16 = (cok && okB[1]) ? pb[t][1] : 0u;
+      const int col = c * 16 + ta * 4 + tb;
+      *reinterpret_cast<uint32_t*>(Bs + col * kDwCells + 2 * k2) = lo | (hi16 << 16);
     }
   };
   // this wave's steps: cell rows g_lo + wave, + 4, ...; 32-cell steps within each
