@@ -202,7 +202,10 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
  *        only. Overwritten (not accumulated). Deterministic: the summation
  *        order is fixed by the sizes alone.
  *   x  : needed iff dw != NULL. weight: needed for learned methods iff dx != NULL.
- *   LEARNED_MIX4 has no backward in this version (FCFS_E_UNSUPPORTED).
+ *   LEARNED_MIX4 (16-bit storage): weight [p_h][p_w][c_out][c_in][4][4] in
+ *        the storage type, 16-byte aligned; dx[c] sums over every output
+ *        channel o too; dw is FP32 [p_h][p_w][c_out][c_in][4][4]. FP32
+ *        storage returns FCFS_E_UNSUPPORTED, as for the forward.
  *   workspace / ws_bytes: device scratch of at least fcfs_backward_workspace
  *        bytes (NULL allowed when that is 0).
  * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small,
