@@ -12,10 +12,12 @@
 // A workgroup takes 256 columns of one input row and 32 input channels, one
 // column per thread and the 32 channels in registers. The row's height
 // entries are the same for every thread, so for each (height entry, chunk of
-// 8 outputs) the weights of every width phase and tap are staged in LDS as
-// [jw][b][o][c] and each thread adds, for each of its width entries and each
-// output, one dy sample times 32 weights (8 broadcast 16-byte reads). Every
-// sum runs in a fixed order; there are no atomics.
+// 16 outputs) the weights of every width phase and tap are staged in LDS as
+// [jw][b][output pair][c] words of two 16-bit weights, and each thread adds,
+// for each of its width entries and each output pair, the pair of dy samples
+// times 32 weight pairs with v_dot2 (two products into an FP32 accumulator;
+// 8 broadcast 16-byte reads). Every sum runs in a fixed order; there are no
+// atomics.
 //
 // Weight gradient (dw_mix_partial_kernel, dw_mix_reduce_kernel): for each
 // phase a GEMM over cells, dW[o][(c, a, b)] = sum over cells of
@@ -46,17 +48,35 @@ using mix::u16x8;
 
 constexpr int kThreads = 256;
 constexpr int kDxChannels = 32;   // input channels per input-gradient workgroup
-constexpr int kDxOuts = 8;        // outputs per staged weight slice
-// One (jw, b) block of the slice is kDxOuts x kDxChannels floats (1 KB); the
-// blocks sit 1 KB + 16 B apart, so that the lanes of a half-wave, which read
-// from up to p_w * 4 blocks, hit different LDS banks.
-constexpr int kDxBlock = kDxOuts * kDxChannels + 4;
+constexpr int kDxPairs = 8;       // output pairs (16 outputs) per staged weight slice
+// One (jw, b) block of the slice is kDxPairs x kDxChannels words (two 16-bit
+// weights of consecutive outputs each, 1 KB); blocks sit 1 KB + 16 B apart,
+// so that the lanes of a half-wave, which read from up to p_w * 4 blocks, hit
+// different LDS banks.
+constexpr int kDxBlock = kDxPairs * kDxChannels + 4;
+
+// v_dot2 (two 16-bit products added to an FP32 accumulator) for each storage type
+template <int DT> struct Dot2;
+template <> struct Dot2<FCFS_BF16> {
+  typedef __bf16 v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ float dot(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2, a), __builtin_bit_cast(v2, b), c, false);
+  }
+};
+template <> struct Dot2<FCFS_F16> {
+  typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ float dot(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(v2, a), __builtin_bit_cast(v2, b), c, false);
+  }
+};
 
 template <int DT>
 __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
   using S = Store<DT>;
   using TS = typename S::T;
-  extern __shared__ float smem[];   // [p_w * 4 blocks of kDxBlock][kDxOuts][kDxChannels]
+  using D2 = Dot2<DT>;
+  extern __shared__ float smem[];   // p_w * 4 blocks of kDxBlock words: [pair][c]
+  uint32_t* const wl = reinterpret_cast<uint32_t*>(smem);
   const AxisTable& TW = a.tw_tab;
   int64_t blk = blockIdx.x;
   const int cblk = (int)(blk % a.mix_cblocks); blk /= a.mix_cblocks;
@@ -70,52 +90,59 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
   const int* rw = a.tab_w + (int64_t)(live ? j : 0) * (3 + a.cmax_w);
   const int nh = rh[0], nw = live ? rw[0] : 0;
   const uint16_t* wt = reinterpret_cast<const uint16_t*>(a.mix_weight);
-  const TS* dyn = reinterpret_cast<const TS*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo;
+  const uint16_t* dyn = reinterpret_cast<const uint16_t*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo;
   const int64_t oplane = (int64_t)a.Ho * a.Wo;
   float acc[kDxChannels];
 #pragma unroll
   for (int c = 0; c < kDxChannels; ++c) acc[c] = 0.f;
 
-  for (int o0 = 0; o0 < a.Cout; o0 += kDxOuts) {
+  for (int o0 = 0; o0 < a.Cout; o0 += 2 * kDxPairs) {
     for (int eh = 0; eh < nh; ++eh) {
       const int ent = rh[3 + eh];
       const int kh = ent >> 7, jh = (ent >> 2) & 31, ta = ent & 3;
       __syncthreads();   // the previous slice is consumed
-      // stage W[jh][jw][o0 + o][c0 + c][ta][0..3] for every jw, o, c
-      for (int it = threadIdx.x; it < TW.p * kDxOuts * kDxChannels; it += kThreads) {
-        const int c = it % kDxChannels, o = (it / kDxChannels) % kDxOuts, jw = it / (kDxChannels * kDxOuts);
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (o0 + o < a.Cout && c0 + c < a.C) {
-          const uint16_t* src =
-              wt + ((((int64_t)jh * TW.p + jw) * a.Cout + o0 + o) * a.C + c0 + c) * 16 + ta * 4;
-          const uint2 raw = *reinterpret_cast<const uint2*>(src);   // 4 taps, 8-byte aligned
-          v[0] = S::from_bits(raw.x & 0xffffu);
-          v[1] = S::from_bits(raw.x >> 16);
-          v[2] = S::from_bits(raw.y & 0xffffu);
-          v[3] = S::from_bits(raw.y >> 16);
-        }
+      // stage W[jh][jw][o][c0 + c][ta][0..3] for o = o0 + 2 pr, + 1: words
+      // (W[o], W[o + 1]) per (jw, b, pr, c); missing outputs and channels are 0
+      for (int it = threadIdx.x; it < TW.p * kDxPairs * kDxChannels; it += kThreads) {
+        const int c = it % kDxChannels, pr = (it / kDxChannels) % kDxPairs, jw = it / (kDxChannels * kDxPairs);
+        uint2 r[2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) smem[(jw * 4 + b) * kDxBlock + o * kDxChannels + c] = v[b];
+        for (int h = 0; h < 2; ++h) {
+          const int o = o0 + 2 * pr + h;
+          r[h] = make_uint2(0u, 0u);
+          if (o < a.Cout && c0 + c < a.C)   // 4 taps, 8-byte aligned
+            r[h] = *reinterpret_cast<const uint2*>(wt + ((((int64_t)jh * TW.p + jw) * a.Cout + o) * a.C + c0 + c) * 16 + ta * 4);
+        }
+        uint32_t* dst = wl + (jw * 4) * kDxBlock + pr * kDxChannels + c;
+        dst[0 * kDxBlock] = __builtin_amdgcn_perm(r[1].x, r[0].x, 0x05040100u);
+        dst[1 * kDxBlock] = __builtin_amdgcn_perm(r[1].x, r[0].x, 0x07060302u);
+        dst[2 * kDxBlock] = __builtin_amdgcn_perm(r[1].y, r[0].y, 0x05040100u);
+        dst[3 * kDxBlock] = __builtin_amdgcn_perm(r[1].y, r[0].y, 0x07060302u);
       }
       __syncthreads();
-      const TS* dyr = dyn + (int64_t)o0 * oplane + (int64_t)kh * a.Wo;
+      const uint16_t* dyr = dyn + (int64_t)o0 * oplane + (int64_t)kh * a.Wo;
       for (int ew = 0; ew < nw; ++ew) {
         const int went = rw[3 + ew];
         const int kw = went >> 7, jw = (went >> 2) & 31, tb = went & 3;
-        const float* ws = smem + (jw * 4 + tb) * kDxBlock;
-        float dv[kDxOuts];
+        const uint32_t* ws = wl + (jw * 4 + tb) * kDxBlock;
+        uint32_t dv[kDxPairs];   // (dy[o], dy[o + 1]) as one word; missing outputs read as 0
 #pragma unroll
-        for (int o = 0; o < kDxOuts; ++o) dv[o] = (o0 + o < a.Cout) ? S::load(dyr + o * oplane + kw) : 0.f;
+        for (int pr = 0; pr < kDxPairs; ++pr) {
+          const int o = o0 + 2 * pr;
+          const uint32_t lo = o < a.Cout ? dyr[(int64_t)(2 * pr) * oplane + kw] : 0u;
+          const uint32_t hi = o + 1 < a.Cout ? dyr[(int64_t)(2 * pr + 1) * oplane + kw] : 0u;
+          dv[pr] = lo | (hi << 16);
+        }
 #pragma unroll
-        for (int o = 0; o < kDxOuts; ++o) {
-          const float4* w4 = reinterpret_cast<const float4*>(ws + o * kDxChannels);
+        for (int pr = 0; pr < kDxPairs; ++pr) {
+          const uint4* w4 = reinterpret_cast<const uint4*>(ws + pr * kDxChannels);
 #pragma unroll
           for (int q4 = 0; q4 < kDxChannels / 4; ++q4) {
-            const float4 w = w4[q4];
-            acc[4 * q4 + 0] = __builtin_fmaf(w.x, dv[o], acc[4 * q4 + 0]);
-            acc[4 * q4 + 1] = __builtin_fmaf(w.y, dv[o], acc[4 * q4 + 1]);
-            acc[4 * q4 + 2] = __builtin_fmaf(w.z, dv[o], acc[4 * q4 + 2]);
-            acc[4 * q4 + 3] = __builtin_fmaf(w.w, dv[o], acc[4 * q4 + 3]);
+            const uint4 w = w4[q4];
+            acc[4 * q4 + 0] = D2::dot(w.x, dv[pr], acc[4 * q4 + 0]);
+            acc[4 * q4 + 1] = D2::dot(w.y, dv[pr], acc[4 * q4 + 1]);
+            acc[4 * q4 + 2] = D2::dot(w.z, dv[pr], acc[4 * q4 + 2]);
+            acc[4 * q4 + 3] = D2::dot(w.w, dv[pr], acc[4 * q4 + 3]);
           }
         }
       }
@@ -294,7 +321,7 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   if (a.dx) {
     const int64_t blocks = (int64_t)a.planes_n * a.H * a.col_blocks * a.mix_cblocks;
-    const size_t lds = sizeof(float) * a.tw_tab.p * 4 * kDxBlock;
+    const size_t lds = sizeof(uint32_t) * a.tw_tab.p * 4 * kDxBlock;
     hipLaunchKernelGGL((dx_mix_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }

@@ -60,6 +60,11 @@ inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); r
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 #define __builtin_nontemporal_load(p) (*(p))
 
+// v_dot2 of two pairs of 16-bit values into an FP32 accumulator
+template <class V>
+inline float hostemu_dot2(V a, V b, float c) { return (float)a[0] * (float)b[0] + (float)a[1] * (float)b[1] + c; }
+#define __builtin_amdgcn_fdot2_f32_bf16(a, b, c, clamp) hostemu_dot2(a, b, c)
+#define __builtin_amdgcn_fdot2(a, b, c, clamp) hostemu_dot2(a, b, c)
 // v_perm_b32: byte i of the result is byte sel[i] of the 8-byte value whose
 // low word is b and high word is a (selectors 0..7 only).
 inline uint32_t __builtin_amdgcn_perm(uint32_t a, uint32_t b, uint32_t sel) {
@@ -105,6 +110,7 @@ struct uint4 {
 struct uint2 {
   unsigned x, y;
 };
+inline uint2 make_uint2(unsigned x, unsigned y) { return uint2{x, y}; }
 struct float4 {
   float x, y, z, w;
 };
