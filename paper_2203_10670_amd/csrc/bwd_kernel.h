@@ -9,6 +9,9 @@
 // are kept in ascending e, j, t order, so every sum below runs in a fixed
 // order. Table row i: [count, first k, last k, entry 0, entry 1, ...], an
 // entry packing (k << 7) | (j << 2) | t (output index k = p*m + j < 2^24).
+// The height table keeps each row contiguous (a workgroup reads one row);
+// the width table stores field f of column j at f * W + j, so that the
+// consecutive columns of a wave read consecutive words.
 //
 // Input gradient. One thread per input sample: dx[i][c] = sum over the row
 // entries (kh, th) and column entries (kw, tw) of w * dy[kh][kw], where w is
@@ -38,6 +41,20 @@ using fwd::pad_source;
 using fwd::Store;
 
 constexpr int kThreads = 256;
+#ifndef FCFS_BWD_DX_ROWS
+#define FCFS_BWD_DX_ROWS 8
+#endif
+constexpr int kDxRows = FCFS_BWD_DX_ROWS;   // input rows per input-gradient workgroup
+
+// Block b runs on XCD b % 8. The logical order the kernels below decode
+// gives each XCD a contiguous range, so that neighbouring rows (which read
+// the same output-gradient rows) share one L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  int64_t blk = blockIdx.x;
+  const int64_t per = (int64_t)gridDim.x / 8;
+  if (blk < 8 * per) blk = (blk % 8) * per + blk / 8;
+  return blk;
+}
 
 // Setup: the adjoint tables of both axes (rows 0..H-1 of the height axis,
 // then 0..W-1 of the width axis).
@@ -51,7 +68,8 @@ __global__ __launch_bounds__(kThreads) void adjoint_tables_kernel(const BwdArgs 
   const int n = height ? a.H : a.W;
   const int cells = height ? a.Mh : a.Mw;
   const int cmax = height ? a.cmax_h : a.cmax_w;
-  int* row = (height ? a.tab_h : a.tab_w) + (int64_t)i * (3 + cmax);
+  int* row = height ? a.tab_h + (int64_t)i * (3 + cmax) : a.tab_w + i;
+  const int64_t fs = height ? 1 : a.W;   // field stride
   const int emin = t.omin, emax = t.q * (cells - 1) + t.omax;
   int cnt = 0, klo = 1 << 30, khi = -1;
   auto add_position = [&](int e) {
@@ -62,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_tables_kernel(const BwdArgs 
         const int m = d / t.q;
         if (m >= cells) continue;
         const int k = t.p * m + j;
-        if (cnt < cmax) row[3 + cnt] = (k << 7) | (j << 2) | tap;
+        if (cnt < cmax) row[(3 + cnt) * fs] = (k << 7) | (j << 2) | tap;
         ++cnt;
         klo = min(klo, k);
         khi = max(khi, k);
@@ -74,8 +92,8 @@ __global__ __launch_bounds__(kThreads) void adjoint_tables_kernel(const BwdArgs 
   for (int e = n; e <= emax; ++e)
     if (pad_source(e, n, a.pad) == i) add_position(e);
   row[0] = min(cnt, cmax);
-  row[1] = klo;
-  row[2] = khi;
+  row[fs] = klo;
+  row[2 * fs] = khi;
 }
 
 // FE: width entries of a column held in registers (4 or 8, at least the
@@ -89,11 +107,15 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
   extern __shared__ float smem[];   // learned: this channel's taps [p_h][p_w][4][4]
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
-  const int64_t per_plane_blocks = (int64_t)a.H * a.col_blocks;
-  const int64_t plane = blockIdx.x / per_plane_blocks;
-  const int64_t rem = blockIdx.x - plane * per_plane_blocks;
-  const int i = (int)(rem / a.col_blocks);
-  const int j = (int)(rem % a.col_blocks) * kThreads + threadIdx.x;
+  // a workgroup: kDxRows consecutive rows of one plane, 256 columns; the
+  // column's width entries and the plane's weights are set up once for them
+  const int row_groups = (a.H + kDxRows - 1) / kDxRows;
+  const int64_t per_plane_blocks = (int64_t)row_groups * a.col_blocks;
+  const int64_t lblk = xcd_block();
+  const int64_t plane = lblk / per_plane_blocks;
+  const int rem = (int)(lblk - plane * per_plane_blocks);
+  const int i0 = (rem / a.col_blocks) * kDxRows;
+  const int j = (rem % a.col_blocks) * kThreads + threadIdx.x;
   if constexpr (LEARNED) {
     const int nwt = TH.p * TW.p * 16;
     const float* wsrc = a.weight + (int64_t)(plane % a.C) * nwt;
@@ -101,9 +123,9 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
     __syncthreads();
   }
   if (plane >= a.planes || j >= a.W) return;
-  const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
-  const int* rw = a.tab_w + (int64_t)j * (3 + a.cmax_w);
-  const int nh = rh[0], nw = rw[0];
+  const int* rw = a.tab_w + j;   // field f at f * W
+  const int64_t fw = a.W;
+  const int nw = rw[0];
   // this column's width entries: output column, and the tap weight (fixed
   // methods) or the weight's offset within a height phase's block (learned)
   int kw[kFastEntries];
@@ -111,44 +133,49 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
   float ww[kFastEntries];
 #pragma unroll
   for (int e = 0; e < kFastEntries; ++e) {
-    const int ent = e < nw ? rw[3 + e] : 0;
+    const int ent = e < nw ? rw[(3 + e) * fw] : 0;
     const int jw = (ent >> 2) & 31, tw = ent & 3;
     kw[e] = ent >> 7;
     wo[e] = jw * 16 + tw;
     ww[e] = LEARNED ? 0.f : TW.w[jw][tw];
   }
   const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
-  float acc = 0.f;
-  for (int eh = 0; eh < nh; ++eh) {
-    const int ent = rh[3 + eh];
-    const int kh = ent >> 7, jh = (ent >> 2) & 31, th = ent & 3;
-    const TS* dyrow = dyp + (int64_t)kh * a.Wo;
-    float v[kFastEntries];
-#pragma unroll
-    for (int e = 0; e < kFastEntries; ++e) v[e] = S::load(dyrow + kw[e]);   // all issued first
-    if constexpr (LEARNED) {
-      const float* wr = smem + jh * TW.p * 16 + th * 4;
-#pragma unroll
-      for (int e = 0; e < kFastEntries; ++e)
-        if (e < nw) acc = __builtin_fmaf(wr[wo[e]], v[e], acc);
-      for (int e = kFastEntries; e < nw; ++e) {
-        const int we = rw[3 + e];
-        acc = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc);
-      }
-    } else {
-      float inner = 0.f;
-#pragma unroll
-      for (int e = 0; e < kFastEntries; ++e)
-        if (e < nw) inner = __builtin_fmaf(ww[e], v[e], inner);
-      for (int e = kFastEntries; e < nw; ++e) {
-        const int we = rw[3 + e];
-        inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
-      }
-      acc = __builtin_fmaf(TH.w[jh][th], inner, acc);
-    }
-  }
   TS* dxp = reinterpret_cast<TS*>(a.dx) + plane * (int64_t)a.H * a.W;
-  S::store(dxp + (int64_t)i * a.W + j, acc);
+  const int i1 = min(i0 + kDxRows, a.H);
+  for (int i = i0; i < i1; ++i) {
+    const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
+    const int nh = rh[0];
+    float acc = 0.f;
+    for (int eh = 0; eh < nh; ++eh) {
+      const int ent = rh[3 + eh];
+      const int kh = ent >> 7, jh = (ent >> 2) & 31, th = ent & 3;
+      const TS* dyrow = dyp + (int64_t)kh * a.Wo;
+      float v[kFastEntries];
+#pragma unroll
+      for (int e = 0; e < kFastEntries; ++e) v[e] = S::load(dyrow + kw[e]);   // all issued first
+      if constexpr (LEARNED) {
+        const float* wr = smem + jh * TW.p * 16 + th * 4;
+#pragma unroll
+        for (int e = 0; e < kFastEntries; ++e)
+          if (e < nw) acc = __builtin_fmaf(wr[wo[e]], v[e], acc);
+        for (int e = kFastEntries; e < nw; ++e) {
+          const int we = rw[(3 + e) * fw];
+          acc = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc);
+        }
+      } else {
+        float inner = 0.f;
+#pragma unroll
+        for (int e = 0; e < kFastEntries; ++e)
+          if (e < nw) inner = __builtin_fmaf(ww[e], v[e], inner);
+        for (int e = kFastEntries; e < nw; ++e) {
+          const int we = rw[(3 + e) * fw];
+          inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
+        }
+        acc = __builtin_fmaf(TH.w[jh][th], inner, acc);
+      }
+    }
+    S::store(dxp + (int64_t)i * a.W + j, acc);
+  }
 }
 
 // Weight gradient, stage 1: per-chunk partial sums. A chunk is ch x cw cells
@@ -160,8 +187,9 @@ __global__ __launch_bounds__(kThreads) void dw_partial_kernel(const BwdArgs a) {
   extern __shared__ float smem[];
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
-  const int c = blockIdx.x / a.chunks_per_channel;
-  const int r = blockIdx.x % a.chunks_per_channel;
+  const int64_t lblk = xcd_block();
+  const int c = (int)(lblk / a.chunks_per_channel);
+  const int r = (int)(lblk % a.chunks_per_channel);
   const int n = r / (a.nch * a.ncw);
   const int cb = r % (a.nch * a.ncw);
   const int mh0 = (cb / a.ncw) * a.ch, mw0 = (cb % a.ncw) * a.cw;
@@ -291,7 +319,7 @@ fcfs_status launch_backward_dt(const BwdArgs& a, bool learned, hipStream_t strea
                      block, 0, stream, a);
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   if (a.dx) {
-    const int64_t blocks = a.planes * (int64_t)a.H * a.col_blocks;
+    const int64_t blocks = a.planes * (int64_t)((a.H + kDxRows - 1) / kDxRows) * a.col_blocks;
     const size_t wl = sizeof(float) * a.th.p * a.tw_tab.p * 16;
     const dim3 grid((unsigned)blocks);
     if (a.fast_w <= 4) {

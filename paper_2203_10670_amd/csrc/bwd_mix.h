@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
   extern __shared__ float smem[];   // p_w * 4 blocks of kDxBlock words: [pair][c]
   uint32_t* const wl = reinterpret_cast<uint32_t*>(smem);
   const AxisTable& TW = a.tw_tab;
-  int64_t blk = blockIdx.x;
+  int64_t blk = bwd::xcd_block();
   const int cblk = (int)(blk % a.mix_cblocks); blk /= a.mix_cblocks;
   const int colb = (int)(blk % a.col_blocks); blk /= a.col_blocks;
   const int i = (int)(blk % a.H);
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
   const int j = colb * kThreads + threadIdx.x;
   const bool live = j < a.W;
   const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
-  const int* rw = a.tab_w + (int64_t)(live ? j : 0) * (3 + a.cmax_w);
+  const int* rw = a.tab_w + (live ? j : 0);   // field f at f * W
   const int nh = rh[0], nw = live ? rw[0] : 0;
   const uint16_t* wt = reinterpret_cast<const uint16_t*>(a.mix_weight);
   const uint16_t* dyn = reinterpret_cast<const uint16_t*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
       __syncthreads();
       const uint16_t* dyr = dyn + (int64_t)o0 * oplane + (int64_t)kh * a.Wo;
       for (int ew = 0; ew < nw; ++ew) {
-        const int went = rw[3 + ew];
+        const int went = rw[(int64_t)(3 + ew) * a.W];
         const int kw = went >> 7, jw = (went >> 2) & 31, tb = went & 3;
         const uint32_t* ws = wl + (jw * 4 + tb) * kDxBlock;
         uint32_t dv[kDxPairs];   // (dy[o], dy[o + 1]) as one word; missing outputs read as 0
