@@ -205,7 +205,7 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     int side = 16;
     auto lds_floats = [&](int ch, int cw) {
       const int xr = th.q * (ch - 1) + th.omax - th.omin + 1, xc = tw.q * (cw - 1) + tw.omax - tw.omin + 1;
-      return th.p * ch * tw.p * cw + xr * xc + (256 / P2) * P2 * 16;
+      return std::max(th.p * ch * tw.p * cw + xr * xc, (256 / P2) * P2 * 16);   // the sums reuse the patches' space
     };
     while (side > 1 && lds_floats(side, side) > 14336) --side;
     a->ch = std::min(side, a->Mh);

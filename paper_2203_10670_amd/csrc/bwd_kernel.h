@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void dw_partial_kernel(const BwdArgs a) {
   const int xc = TW.q * (mw1 - mw0 - 1) + TW.omax - TW.omin + 1;
   float* dys = smem;
   float* xs = smem + dyr * dyc;
-  float* red = xs + xr * xc;   // [subsets][phases][16]
+  float* red = smem;           // [subsets][phases][16], over the staged patches once they are used
   const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
   const TS* xp = reinterpret_cast<const TS*>(a.x) + plane * (int64_t)a.H * a.W;
   // rows by wave, columns by lane (128-column blocks); loads of four rows
@@ -262,16 +262,24 @@ __global__ __launch_bounds__(kThreads) void dw_partial_kernel(const BwdArgs a) {
   if (sub < subsets) {
     const int jh = phase / TW.p, jw = phase % TW.p;
     const int oh = TH.off[jh] - TH.omin, ow = TW.off[jw] - TW.omin;
-    const int ncell = (mh1 - mh0) * (mw1 - mw0);
-    for (int cell = sub; cell < ncell; cell += subsets) {
-      const int lh = cell / (mw1 - mw0), lw = cell % (mw1 - mw0);
+    const int cw = mw1 - mw0;
+    int lh = sub / cw, lw = sub % cw;   // cell sub, then every subsets-th cell (no division per cell)
+    for (; lh < mh1 - mh0;) {
       const float g = dys[(TH.p * lh + jh) * dyc + TW.p * lw + jw];
       const float* xb = xs + (TH.q * lh + oh) * xc + TW.q * lw + ow;
 #pragma unroll
       for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
         for (int tb = 0; tb < 4; ++tb) acc[ta * 4 + tb] = __builtin_fmaf(g, xb[ta * xc + tb], acc[ta * 4 + tb]);
+      lw += subsets;
+      while (lw >= cw) {
+        lw -= cw;
+        ++lh;
+      }
     }
+  }
+  __syncthreads();   // the staged patches are no longer read
+  if (sub < subsets) {
     float* rp = red + (sub * P2 + phase) * 16;
 #pragma unroll
     for (int k = 0; k < 16; ++k) rp[k] = acc[k];
