@@ -45,6 +45,7 @@ constexpr int kThreads = 256;
 #define FCFS_BWD_DX_ROWS 8
 #endif
 constexpr int kDxRows = FCFS_BWD_DX_ROWS;   // input rows per input-gradient workgroup
+constexpr int kDxPlanes = 4;                 // planes per input-gradient workgroup
 
 // Block b runs on XCD b % 8. The logical order the kernels below decode
 // gives each XCD a contiguous range, so that neighbouring rows (which read
@@ -104,25 +105,31 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
   constexpr int kFastEntries = FE;
   using S = Store<DT>;
   using TS = typename S::T;
-  extern __shared__ float smem[];   // learned: this channel's taps [p_h][p_w][4][4]
+  extern __shared__ float smem[];   // learned: the planes' taps [plane][p_h][p_w][4][4]
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
-  // a workgroup: kDxRows consecutive rows of one plane, 256 columns; the
-  // column's width entries and the plane's weights are set up once for them
+  // A workgroup: kDxRows consecutive rows of kDxPlanes consecutive planes,
+  // 256 columns. The column's width entries and the planes' weights are set
+  // up once; each row's height entries (decoded by the scalar unit) serve
+  // all the planes.
   const int row_groups = (a.H + kDxRows - 1) / kDxRows;
-  const int64_t per_plane_blocks = (int64_t)row_groups * a.col_blocks;
+  const int64_t per_group_blocks = (int64_t)row_groups * a.col_blocks;
   const int64_t lblk = xcd_block();
-  const int64_t plane = lblk / per_plane_blocks;
-  const int rem = (int)(lblk - plane * per_plane_blocks);
+  const int64_t pgroup = lblk / per_group_blocks;
+  const int rem = (int)(lblk - pgroup * per_group_blocks);
   const int i0 = (rem / a.col_blocks) * kDxRows;
   const int j = (rem % a.col_blocks) * kThreads + threadIdx.x;
+  const int64_t plane0 = pgroup * kDxPlanes;
+  const int np = (int)min((int64_t)kDxPlanes, a.planes - plane0);
+  const int nwt = TH.p * TW.p * 16;
   if constexpr (LEARNED) {
-    const int nwt = TH.p * TW.p * 16;
-    const float* wsrc = a.weight + (int64_t)(plane % a.C) * nwt;
-    for (int k = threadIdx.x; k < nwt; k += kThreads) smem[k] = wsrc[k];
+    for (int k = threadIdx.x; k < kDxPlanes * nwt; k += kThreads) {
+      const int pl = k / nwt;
+      smem[k] = pl < np ? a.weight[(int64_t)((plane0 + pl) % a.C) * nwt + k % nwt] : 0.f;
+    }
     __syncthreads();
   }
-  if (plane >= a.planes || j >= a.W) return;
+  if (j >= a.W) return;
   const int* rw = a.tab_w + j;   // field f at f * W
   const int64_t fw = a.W;
   const int nw = rw[0];
@@ -139,42 +146,57 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
     wo[e] = jw * 16 + tw;
     ww[e] = LEARNED ? 0.f : TW.w[jw][tw];
   }
-  const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane * (int64_t)a.Ho * a.Wo;
-  TS* dxp = reinterpret_cast<TS*>(a.dx) + plane * (int64_t)a.H * a.W;
+  const int64_t oplane = (int64_t)a.Ho * a.Wo, iplane = (int64_t)a.H * a.W;
+  const TS* dyp = reinterpret_cast<const TS*>(a.dy) + plane0 * oplane;
+  TS* dxp = reinterpret_cast<TS*>(a.dx) + plane0 * iplane;
   const int i1 = min(i0 + kDxRows, a.H);
   for (int i = i0; i < i1; ++i) {
     const int* rh = a.tab_h + (int64_t)i * (3 + a.cmax_h);
     const int nh = rh[0];
-    float acc = 0.f;
+    float acc[kDxPlanes];
+#pragma unroll
+    for (int k = 0; k < kDxPlanes; ++k) acc[k] = 0.f;
     for (int eh = 0; eh < nh; ++eh) {
       const int ent = rh[3 + eh];
       const int kh = ent >> 7, jh = (ent >> 2) & 31, th = ent & 3;
-      const TS* dyrow = dyp + (int64_t)kh * a.Wo;
-      float v[kFastEntries];
+      // every plane's samples are requested before the first FMA (planes
+      // past the last read the first one's, and are not stored)
+      float vv[kDxPlanes][kFastEntries];
 #pragma unroll
-      for (int e = 0; e < kFastEntries; ++e) v[e] = S::load(dyrow + kw[e]);   // all issued first
-      if constexpr (LEARNED) {
-        const float* wr = smem + jh * TW.p * 16 + th * 4;
+      for (int k = 0; k < kDxPlanes; ++k) {
+        const TS* dyrow = dyp + (k < np ? k : 0) * oplane + (int64_t)kh * a.Wo;
 #pragma unroll
-        for (int e = 0; e < kFastEntries; ++e)
-          if (e < nw) acc = __builtin_fmaf(wr[wo[e]], v[e], acc);
-        for (int e = kFastEntries; e < nw; ++e) {
-          const int we = rw[(3 + e) * fw];
-          acc = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc);
+        for (int e = 0; e < kFastEntries; ++e) vv[k][e] = S::load(dyrow + kw[e]);
+      }
+#pragma unroll
+      for (int k = 0; k < kDxPlanes; ++k) {
+        const TS* dyrow = dyp + (k < np ? k : 0) * oplane + (int64_t)kh * a.Wo;
+        const float* v = vv[k];
+        if constexpr (LEARNED) {
+          const float* wr = smem + k * nwt + jh * TW.p * 16 + th * 4;
+#pragma unroll
+          for (int e = 0; e < kFastEntries; ++e)
+            if (e < nw) acc[k] = __builtin_fmaf(wr[wo[e]], v[e], acc[k]);
+          for (int e = kFastEntries; e < nw; ++e) {
+            const int we = rw[(3 + e) * fw];
+            acc[k] = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc[k]);
+          }
+        } else {
+          float inner = 0.f;
+#pragma unroll
+          for (int e = 0; e < kFastEntries; ++e)
+            if (e < nw) inner = __builtin_fmaf(ww[e], v[e], inner);
+          for (int e = kFastEntries; e < nw; ++e) {
+            const int we = rw[(3 + e) * fw];
+            inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
+          }
+          acc[k] = __builtin_fmaf(TH.w[jh][th], inner, acc[k]);
         }
-      } else {
-        float inner = 0.f;
-#pragma unroll
-        for (int e = 0; e < kFastEntries; ++e)
-          if (e < nw) inner = __builtin_fmaf(ww[e], v[e], inner);
-        for (int e = kFastEntries; e < nw; ++e) {
-          const int we = rw[(3 + e) * fw];
-          inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
-        }
-        acc = __builtin_fmaf(TH.w[jh][th], inner, acc);
       }
     }
-    S::store(dxp + (int64_t)i * a.W + j, acc);
+#pragma unroll
+    for (int k = 0; k < kDxPlanes; ++k)
+      if (k < np) S::store(dxp + k * iplane + (int64_t)i * a.W + j, acc[k]);
   }
 }
 
@@ -327,8 +349,9 @@ fcfs_status launch_backward_dt(const BwdArgs& a, bool learned, hipStream_t strea
                      block, 0, stream, a);
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   if (a.dx) {
-    const int64_t blocks = a.planes * (int64_t)((a.H + kDxRows - 1) / kDxRows) * a.col_blocks;
-    const size_t wl = sizeof(float) * a.th.p * a.tw_tab.p * 16;
+    const int64_t blocks =
+        ((a.planes + kDxPlanes - 1) / kDxPlanes) * (int64_t)((a.H + kDxRows - 1) / kDxRows) * a.col_blocks;
+    const size_t wl = sizeof(float) * kDxPlanes * a.th.p * a.tw_tab.p * 16;
     const dim3 grid((unsigned)blocks);
     if (a.fast_w <= 4) {
       if (learned) hipLaunchKernelGGL((dx_kernel<DT, true, 4>), grid, block, wl, stream, a);
