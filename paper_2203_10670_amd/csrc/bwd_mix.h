@@ -159,9 +159,16 @@ constexpr int kDwOuts = 32;   // outputs per weight-gradient workgroup (2 M tile
 constexpr int kDwChan = 8;    // input channels per workgroup: 8 x 16 taps = 128 columns (8 N tiles)
 constexpr int kDwCells = 32;  // cells per MFMA reduction step
 
+constexpr int kRawPitch = 136;   // 16-bit samples per staged x row (128 columns and a bank skew)
+
 // Partial sums of one chunk of cell rows: partial[chunk][phase][o][c][16].
-template <int DT>
-__global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs a) {
+// RAW (q <= 4, so the 31 q + 4 columns of a step's 32 cells fit in 128): the
+// step's x rows are loaded whole, two adjacent columns per lane (coalesced),
+// into LDS rows, and each B fragment gathers its 8 cells from there;
+// otherwise each lane loads the samples of its own (cell pair, b) column.
+template <int DT, bool RAW>
+__global__ __launch_bounds__(kThreads, 2) void dw_mix_partial_kernel(
+    const BwdArgs a) {
   using M = Mfma<DT>;
   extern __shared__ float smem[];
   const AxisTable& TH = a.th;
@@ -177,8 +184,9 @@ __global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, g4 = lane >> 4;
   // wave-private staging: A [32 o][32 cells], B [128 (c, a, b)][32 cells] (16-bit)
-  uint16_t* const As = reinterpret_cast<uint16_t*>(smem) + wave * (kDwOuts + 16 * kDwChan) * kDwCells;
-  uint16_t* const Bs = As + kDwOuts * kDwCells;
+  constexpr int kWaveLds = RAW ? kDwOuts * kDwCells + 4 * kDwChan * kRawPitch : (kDwOuts + 16 * kDwChan) * kDwCells;
+  uint16_t* const As = reinterpret_cast<uint16_t*>(smem) + wave * kWaveLds;
+  uint16_t* const Bs = As + kDwOuts * kDwCells;   // RAW: the x rows [c][ta][kRawPitch]
   const int G = a.planes_n * a.Mh;   // cell rows (n, mh)
   const int g_lo = (int)((int64_t)G * chunk / a.mix_kchunks);
   const int g_hi = (int)((int64_t)G * (chunk + 1) / a.mix_kchunks);
@@ -229,6 +237,18 @@ __global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs 
       for (int e = 0; e < 2; ++e) pa[t][e] = row[colA[e]];
     }
     rowmask = 0;
+    if constexpr (RAW) {
+      // columns cb + 2 lane + e of the step's segment (cb = q mw0 + off_w(jw));
+      // past the step's last tap, or in zero padding, they are masked
+      const int cb = TW.q * mw0 + TW.off[jw];
+      const int used = TW.q * (min(kDwCells, a.Mw - mw0) - 1) + 4;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int sc = pad_source(cb + 2 * lane + e, a.W, a.pad);
+        colB[e] = sc >= 0 ? sc : 0;
+        okB[e] = sc >= 0 && 2 * lane + e < used;
+      }
+    }
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta) {
       const int sr = pad_source(TH.q * mh + TH.off[jh] + ta, a.H, a.pad);
@@ -253,8 +273,12 @@ __global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs 
       const int c = t >> 2, ta = t & 3;
       const bool cok = ((rowmask >> ta) & 1u) && c0 + c < a.C;
       const uint32_t lo = (cok && okB[0]) ? pb[t][0] : 0u, hi16 = (cok && okB[1]) ? pb[t][1] : 0u;
-      const int col = c * 16 + ta * 4 + tb;
-      *reinterpret_cast<uint32_t*>(Bs + col * kDwCells + 2 * k2) = lo | (hi16 << 16);
+      if constexpr (RAW) {
+        *reinterpret_cast<uint32_t*>(Bs + t * kRawPitch + 2 * lane) = lo | (hi16 << 16);
+      } else {
+        const int col = c * 16 + ta * 4 + tb;
+        *reinterpret_cast<uint32_t*>(Bs + col * kDwCells + 2 * k2) = lo | (hi16 << 16);
+      }
     }
   };
   // this wave's steps: cell rows g_lo + wave, + 4, ...; 32-cell steps within each
@@ -271,12 +295,34 @@ __global__ __launch_bounds__(kThreads) void dw_mix_partial_kernel(const BwdArgs 
     u16x8 af[2], bf[8];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) af[mt] = *reinterpret_cast<const u16x8*>(As + (mt * 16 + li) * kDwCells + 8 * g4);
+    if constexpr (RAW) {
+      // column (c, ta, tb) = (nt, li >> 2, li & 3): cells 8 g4 + i sit at
+      // q (8 g4 + i) + tb of x row (c, ta); each fragment is gathered just
+      // before its two MFMAs (the next one's reads are issued first)
+      auto gather = [&](int nt) __attribute__((always_inline)) {
+        const uint16_t* xr = Bs + (nt * 4 + (li >> 2)) * kRawPitch + TW.q * 8 * g4 + (li & 3);
+        u16x8 f;
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) bf[nt] = *reinterpret_cast<const u16x8*>(Bs + (nt * 16 + li) * kDwCells + 8 * g4);
+        for (int i = 0; i < 8; ++i) f[i] = xr[TW.q * i];
+        return f;
+      };
+      bf[0] = gather(0);
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+      for (int nt = 0; nt < 8; ++nt) {
+        if (nt + 1 < 8) bf[nt + 1] = gather(nt + 1);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+        for (int mt = 0; mt < 2; ++mt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt) bf[nt] = *reinterpret_cast<const u16x8*>(Bs + (nt * 16 + li) * kDwCells + 8 * g4);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+    }
     fwd::wave_lds_sync();
   }
   // add the 4 waves' tiles in order (wave 0 first) through LDS, then write
@@ -327,8 +373,9 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
   }
   if (a.dw) {
     const int64_t blocks = (int64_t)a.th.p * a.tw_tab.p * a.mix_otiles * a.mix_ctiles * a.mix_kchunks;
-    const size_t lds = sizeof(float) * 4 * kDwOuts * 128;   // >= the staging (4 x 10 KB)
-    hipLaunchKernelGGL((dw_mix_partial_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);
+    const size_t lds = sizeof(float) * 4 * kDwOuts * 128;   // >= the staging (4 x 11 KB)
+    if (a.tw_tab.q <= 4) hipLaunchKernelGGL((dw_mix_partial_kernel<DT, true>), dim3((unsigned)blocks), block, lds, stream, a);
+    else hipLaunchKernelGGL((dw_mix_partial_kernel<DT, false>), dim3((unsigned)blocks), block, lds, stream, a);
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
     const int64_t per = (int64_t)a.th.p * a.tw_tab.p * a.Cout * a.C * 16;
     hipLaunchKernelGGL((dw_mix_reduce_kernel), dim3((unsigned)((per + kThreads - 1) / kThreads)), block, 0, stream, a);
