@@ -201,19 +201,29 @@ __device__ __forceinline__ void fwd_wave(const FwdArgs& a, int64_t wid, int wslo
     for (int b = 0; b < T; ++b) wc[c][b] = LEARNED ? 0.f : TW.w[jw][b];
   }
 
+  // Last staged column any tap of this strip reads (positions are
+  // nondecreasing in the output column). Slots past it load that column
+  // again instead of the next strip's samples, so a wave fetches only what
+  // it uses (their staged values are never read).
+  int need;
+  {
+    const int n = (owEnd - 1) / TW.p;
+    need = TW.q * n + TW.off[owEnd - 1 - n * TW.p] - cs + T - 1;
+  }
+
   // Source column of staged slot s of this lane (single samples: column
-  // cs + lane + 64*s, clamped into the row, ckeep = false where zero padding
-  // supplies the value; pairs: columns cs + 2*(lane + 64*s) + {0, 1}, inside
-  // the row by construction).
+  // cs + min(lane + 64*s, need), clamped into the row, ckeep = false where
+  // zero padding supplies the value; pairs: columns cs + 2*u + {0, 1} with
+  // u = min(lane + 64*s, need / 2), inside the row by construction).
   int scol[L];
   bool ckeep[L];
 #pragma unroll
   for (int s = 0; s < L; ++s) {
     if constexpr (PAIR) {
-      scol[s] = cs + 2 * (lane + 64 * s);
+      scol[s] = cs + 2 * min(lane + 64 * s, need >> 1);
       ckeep[s] = true;
     } else {
-      const int src = pad_source(cs + lane + 64 * s, a.W, a.pad);
+      const int src = pad_source(cs + min(lane + 64 * s, need), a.W, a.pad);
       ckeep[s] = src >= 0;
       scol[s] = src >= 0 ? src : 0;
     }
