@@ -44,7 +44,10 @@ def test_fixed_methods_all_factors():
 def test_wide_rows_multiple_strips_and_bands():
     _run([{"p": 3, "q": 2, "method": "bicubic", "pad": "reflect", "shape": [1, 1, 40, 300]},
           {"p": 2, "q": 3, "method": "bilinear", "pad": "zero", "shape": [1, 1, 30, 700]},
-          {"p": 1, "q": 8, "method": "bicubic", "pad": "replicate", "shape": [1, 1, 33, 1100]}])
+          {"p": 1, "q": 8, "method": "bicubic", "pad": "replicate", "shape": [1, 1, 33, 1100]},
+          # several strips, ragged last one
+          {"p": 3, "q": 2, "method": "bicubic", "pad": "replicate", "shape": [1, 1, 20, 800]},
+          {"p": 5, "q": 4, "method": "bilinear", "pad": "zero", "shape": [1, 2, 12, 900]}])
 
 
 def test_storage_types():
@@ -64,7 +67,8 @@ def test_paired_16bit_io():
     cases = []
     for i, (p, q, m, W) in enumerate([(3, 2, "bicubic", 300), (2, 3, "bilinear", 700), (4, 5, "bicubic", 400),
                                       (5, 4, "bilinear", 208), (3, 4, "bicubic", 256), (27, 11, "nearest", 440),
-                                      (1, 1, "bicubic", 258), (3, 2, "nearest", 132)]):
+                                      (1, 1, "bicubic", 258), (3, 2, "nearest", 132), (3, 2, "bicubic", 800),
+                                      (5, 4, "nearest", 1000)]):
         for dt in ["bf16", "f16"]:
             cases.append({"p": p, "q": q, "method": m, "pad": ["zero", "replicate", "reflect"][i % 3],
                           "dtype": dt, "shape": [1, 2, 11, W], "expect_paired": True})
