@@ -96,7 +96,9 @@ def test_channel_mixing_backward():
     for (p, q, pad, dt, shape, cout) in [(5, 4, "reflect", "bf16", [2, 3, 9, 40], 5),
                                           (3, 2, "zero", "f16", [1, 9, 7, 35], 33),
                                           (2, 3, "replicate", "bf16", [1, 2, 11, 300], 3),
-                                          (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2)]:
+                                          (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2),
+                                          # two column blocks, both columns of a thread live in the first
+                                          (5, 4, "reflect", "bf16", [1, 3, 5, 700], 6)]:
         cases.append({"mode": "bwd", "p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": shape,
                       "cout": cout})
     _run(cases)
