@@ -342,7 +342,7 @@ def measure_serving(count: int, rhos=(0.25, 0.5, 0.8, 0.95)):
 def cpu_baseline(cases, x_np, target_planes: int):
     import oracle
     threads = oracle.threads()
-    k = max(1, min(SHAPE[0] * SHAPE[1], target_planes or 2 * threads))
+    k = max(1, min(SHAPE[0] * SHAPE[1], target_planes or 6 * threads))
     planes = x_np.reshape(-1, SHAPE[2], SHAPE[3])[:k][:, None].astype(np.float64)
     total_bytes = 0
     t0 = time.perf_counter()
