@@ -99,8 +99,14 @@ static fcfs_status forward_geom(const fcfs_plan_* plan, int dtype, int64_t plane
 #ifndef FCFS_FWD_BAND_ROWS16_T4
 #define FCFS_FWD_BAND_ROWS16_T4 32
 #endif
+#ifndef FCFS_FWD_BAND_ROWS_LEARNED
+#define FCFS_FWD_BAND_ROWS_LEARNED 24
+#endif
   const int span_h = ah.omax - ah.omin + 1;
-  const int rows = dtype == FCFS_F32
+  // (the learned depthwise variant loads its phases' weights per wave, so
+  // in FP32 it takes longer bands than bicubic)
+  const int rows = learned && dtype == FCFS_F32 ? FCFS_FWD_BAND_ROWS_LEARNED
+                   : dtype == FCFS_F32
                        ? (ah.T == 1 ? FCFS_FWD_BAND_ROWS_T1 : (ah.T == 2 ? FCFS_FWD_BAND_ROWS_T2 : FCFS_FWD_BAND_ROWS_T4))
                        : (ah.T == 1 ? FCFS_FWD_BAND_ROWS16_T1
                                     : (ah.T == 2 ? FCFS_FWD_BAND_ROWS16_T2 : FCFS_FWD_BAND_ROWS16_T4));

@@ -116,8 +116,9 @@ def test_grids_anisotropic_degenerate():
 @pytest.mark.parametrize("pq", [(3, 4), (3, 2), (5, 4), (2, 11)])
 def test_learned_depthwise(pq):
     p, q = pq
-    _run([{"p": p, "q": q, "method": "dw4", "pad": pad, "shape": [2, 3, 21, 75]}
-          for pad in ["zero", "replicate", "reflect"]])
+    # widths 75 and 300: one ragged strip, or several (two column groups per lane where the output is wider than 64)
+    _run([{"p": p, "q": q, "method": "dw4", "pad": pad, "shape": shape}
+          for pad in ["zero", "replicate", "reflect"] for shape in ([2, 3, 21, 75], [1, 2, 9, 300])])
 
 
 def test_backward_fixed_methods():
