@@ -11,7 +11,11 @@ independent direct sampler that pins it lives in ``oracle.exact``.
 
 Parity unpinned: none of the functions here is unpinned; every one has CPU
 tests against closed forms, exact-rational sampling, library routines or the
-paper's printed kernels.
+paper's printed kernels. The conditioning scales ``condition`` and
+``condition_backward`` are pinned to per-tap sums of |w| |x| (and |w| |dy|,
+|dy| |x| for the gradients) taken in exact rationals over the direct
+sampler's tap lists and the learned layers' 4x4 windows, and to forward(|x|)
+where every weight is non-negative.
 """
 from __future__ import annotations
 
