@@ -242,6 +242,12 @@ typedef struct {
   void* y;               /* device output owned by the caller, or NULL: allocated in the
                             server arena, valid until fcfs_release */
 } fcfs_request;
+/* Ordering of caller-owned buffers: the server runs its kernels on streams of
+ * its own (created non-blocking, so they wait for no other stream, the null
+ * stream included). Whatever writes x, or still reads or writes y, on the
+ * caller's streams must be complete before fcfs_submit (synchronise those
+ * streams first); x must stay unchanged and y untouched until the request's
+ * poll or wait reports it finished. */
 
 typedef struct {
   fcfs_status status;    /* FCFS_OK, or the request's own failure (FCFS_E_NOMEM: larger

@@ -14,6 +14,7 @@ raises, and every call requires tensors that live on a ROCm device.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 __all__ = [
@@ -287,6 +288,11 @@ class Server:
         """Queue a request; x / y are device tensors (or None: generated input
         from ``seed`` / server-owned output). Returns the ticket."""
         n, c, h, w = shape
+        if x is not None or y is not None:
+            # the server's streams do not wait for the caller's: whatever the
+            # caller's stream still has to do with x or y must finish first
+            t = x if x is not None else y
+            _torch().cuda.current_stream(t.device).synchronize()
         req = fcfs_request(p, q, METHODS[method], PADS[pad], DTYPES[dtype], n, c, h, w,
                            None if x is None else _dev_ptr(x), seed, None if y is None else _dev_ptr(y))
         st, t = fcfs_submit(self.handle, req)
@@ -397,13 +403,46 @@ class Plan:
             self.handle = None
 
     # forward / backward on torch tensors -------------------------------
+    def _p_width(self) -> int:
+        return self.pw // math.gcd(self.pw, self.qw)
+
+    def _check_weight(self, weight, act, c_in):
+        """The C ABI reads the weight through a plain pointer whose type and
+        extent follow from the method: refuse anything else here.
+        Fixed methods take none; the depthwise layer an FP32
+        [c_in][p_h][p_w][4][4]; the channel-mixing layer
+        [p_h][p_w][c_out][c_in][4][4] in the activations' type. Returns c_out."""
+        if self.method not in ("dw4", "mix4"):
+            if weight is not None:
+                raise ValueError("method %r takes no weight" % self.method)
+            return c_in
+        if weight is None:
+            raise ValueError("method %r needs a weight" % self.method)
+        if weight.device != act.device:
+            raise ValueError("weight must be on the activations' device")
+        ph, pw = self.p_red, self._p_width()
+        if self.method == "dw4":
+            torch = _torch()
+            if weight.dtype != torch.float32:
+                raise TypeError("the depthwise layer's weight must be float32, got %s" % weight.dtype)
+            want = (c_in, ph, pw, 4, 4)
+            if tuple(weight.shape) != want:
+                raise ValueError("depthwise weight shape %s, expected %s" % (tuple(weight.shape), want))
+            return c_in
+        if weight.dtype != act.dtype:
+            raise TypeError("the channel-mixing weight must have the activations' type %s, got %s"
+                            % (act.dtype, weight.dtype))
+        if weight.dim() != 6 or tuple(weight.shape[:2]) != (ph, pw) or weight.shape[3] != c_in \
+                or tuple(weight.shape[4:]) != (4, 4):
+            raise ValueError("channel-mixing weight shape %s, expected (%d, %d, c_out, %d, 4, 4)"
+                             % (tuple(weight.shape), ph, pw, c_in))
+        return int(weight.shape[2])
+
     def forward(self, x, weight=None, out=None):
         torch = _torch()
         n, c, h, w = x.shape
         ho, wo = self.output_size(h, w)
-        c_out = c
-        if self.method == "mix4":
-            c_out = weight.shape[2]
+        c_out = self._check_weight(weight, x, c)
         if out is None:
             out = torch.empty((n, c_out, ho, wo), dtype=x.dtype, device=x.device)
         st = fcfs_forward(self.handle, _dtype_code(x), n, c, h, w, _dev_ptr(x), _dev_ptr(weight),
@@ -415,6 +454,11 @@ class Plan:
         torch = _torch()
         n, c, h, w = x_shape
         c_out = dy.shape[1]
+        if self.method in ("dw4", "mix4") or weight is not None:
+            if self._check_weight(weight, dy, c) != c_out:
+                raise ValueError("dy has %d channels, the weight %d outputs" % (c_out, weight.shape[2]))
+        if x is not None and (x.dtype != dy.dtype or tuple(x.shape) != tuple(x_shape)):
+            raise ValueError("x must have dy's type and the shape %s" % (tuple(x_shape),))
         dx = torch.empty((n, c, h, w), dtype=dy.dtype, device=dy.device) if need_dx else None
         dw = torch.empty_like(weight, dtype=torch.float32) if need_dw else None
         code = _dtype_code(dy)

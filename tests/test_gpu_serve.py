@@ -69,6 +69,8 @@ def test_caller_owned_buffers():
     pl = fc.Plan(5, 4, "bicubic", "reflect")
     ho, wo = pl.output_size(77, 131)
     y = torch.full((2, 3, ho, wo), 7.0, device="cuda")
+    # the fill runs on torch's stream; the server's streams do not wait for it
+    torch.cuda.synchronize()
     t = srv.submit(5, 4, "bicubic", "reflect", "f32", tuple(x.shape), x=x, y=y)
     r = srv.wait(t)
     assert r.status == 0 and r.y == y.data_ptr()

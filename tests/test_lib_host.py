@@ -193,3 +193,43 @@ def test_nd_entry_points_validate_without_gpu():
     assert fc.fcfs_forward_3d(dw4, phw, 0, n, c, d, h, w, 16, 16, 16, 1 << 30, None) == fc.E_INVAL
     for pl in (one, two, paper, pd, phw, other, pd_paper, phw_paper, dw4):
         fc.fcfs_plan_destroy(pl)
+
+
+def test_binding_refuses_mismatched_weights():
+    # the C ABI reads a learned layer's weight through a plain pointer whose
+    # type and extent follow from the method; the binding checks them first
+    # (these checks run before any device pointer is taken, so CPU tensors do)
+    import torch
+    x = torch.zeros((2, 3, 8, 8))
+    dw = fc.Plan(3, 4, "dw4", "reflect")
+    with pytest.raises(TypeError, match="float32"):
+        dw.forward(x.to(torch.bfloat16), torch.zeros((3, 3, 3, 4, 4), dtype=torch.bfloat16))
+    with pytest.raises(ValueError, match="shape"):
+        dw.forward(x, torch.zeros((3, 3, 3, 4, 3)))
+    with pytest.raises(ValueError, match="shape"):
+        dw.forward(x, torch.zeros((2, 3, 3, 4, 4)))      # channel count
+    with pytest.raises(ValueError, match="needs a weight"):
+        dw.forward(x)
+    # the reduced width factor sizes the phase axis: 6/8 -> 3 phases
+    dw68 = fc.Plan(6, 8, "dw4", "reflect")
+    with pytest.raises(ValueError, match="shape"):
+        dw68.forward(x, torch.zeros((3, 6, 6, 4, 4)))
+    mx = fc.Plan(5, 4, "mix4", "reflect", pw=3, qw=2)
+    xb = x.to(torch.bfloat16)
+    with pytest.raises(TypeError, match="activations' type"):
+        mx.forward(xb, torch.zeros((5, 3, 4, 3, 4, 4)))
+    with pytest.raises(ValueError, match="shape"):
+        mx.forward(xb, torch.zeros((3, 5, 4, 3, 4, 4), dtype=torch.bfloat16))
+    with pytest.raises(ValueError, match="shape"):
+        mx.forward(xb, torch.zeros((5, 3, 4, 2, 4, 4), dtype=torch.bfloat16))
+    with pytest.raises(ValueError, match="takes no weight"):
+        fc.Plan(3, 2, "bicubic", "zero").forward(x, torch.zeros((3, 3, 3, 4, 4)))
+    # a well-formed weight passes the checks and reaches the device-pointer check
+    with pytest.raises(ValueError, match="device tensors"):
+        dw.forward(x, torch.zeros((3, 3, 3, 4, 4)))
+    with pytest.raises(ValueError, match="device tensors"):
+        mx.forward(xb, torch.zeros((5, 3, 7, 3, 4, 4), dtype=torch.bfloat16))
+    # backward: dy's channels must match the mixing weight's outputs
+    with pytest.raises(ValueError, match="outputs"):
+        mx.backward(torch.zeros((2, 6, 10, 12), dtype=torch.bfloat16), (2, 3, 8, 8),
+                    weight=torch.zeros((5, 3, 7, 3, 4, 4), dtype=torch.bfloat16))
