@@ -215,6 +215,31 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
                           hipStream_t stream);
 
+/* Largest workspace fcfs_backward_noalloc can serve: 64 MiB (the 8x64x256^2
+ * learned depthwise backward at 3/4 needs about 4.7 MB, the 16x64x512^2
+ * channel-mixing backward at 5/4 about 52 MB). */
+#define FCFS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* fcfs_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops and harnesses that forbid allocation): the
+ * same kernels and results, with the workspace taken from a fixed device
+ * array of FCFS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends. It allocates nothing; the caller still
+ * passes x, weight, dy, dx and dw as for fcfs_backward. The kernels run on
+ * the stream's device (the current device for the null stream); the first
+ * call on a device looks up that device's array.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from several threads without ordering)
+ * race and give wrong results. Calls ordered on one stream are safe; no call
+ * reads what an earlier one left in the array.
+ * Errors: as fcfs_backward, plus FCFS_E_UNSUPPORTED when these sizes need a
+ * workspace larger than FCFS_NOALLOC_SCRATCH_BYTES (fcfs_backward_workspace
+ * gives the need, with the weight gradient) and FCFS_E_DEVICE when the
+ * array's device address cannot be looked up. */
+fcfs_status fcfs_backward_noalloc(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                                  int64_t w, const void* x, const void* weight, int64_t c_out,
+                                  const void* dy, void* dx, float* dw, hipStream_t stream);
+
 /* ------------------------------------------------------------------ serving
  * A persistent request loop on one GPU (continuous batching). Clients submit
  * rescale requests from any thread; a scheduler thread admits pending

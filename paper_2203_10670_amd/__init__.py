@@ -22,6 +22,7 @@ __all__ = [
     "fcfs_plan", "fcfs_plan_ex", "fcfs_plan_destroy", "fcfs_plan_query", "fcfs_plan_taps",
     "fcfs_output_size",
     "fcfs_forward", "fcfs_forward_config", "fcfs_backward_workspace", "fcfs_backward", "fcfs_status_string",
+    "fcfs_backward_noalloc", "FCFS_NOALLOC_SCRATCH_BYTES",
     "fcfs_version", "Plan", "resize", "FCFSFunction",
     "fcfs_request", "fcfs_result", "fcfs_server_create", "fcfs_submit", "fcfs_poll", "fcfs_wait",
     "fcfs_release", "fcfs_server_stats", "fcfs_server_debug", "fcfs_server_destroy", "Server",
@@ -91,6 +92,7 @@ _sig("fcfs_forward_3d_workspace", [_P, _P, _I, _I64, _I64, _I64, _I64, _I64, cty
 _sig("fcfs_forward_3d", [_P, _P, _I, _I64, _I64, _I64, _I64, _I64, _P, _P, _P, _SZ, _P])
 _sig("fcfs_backward_workspace", [_P, _I, _I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)])
 _sig("fcfs_backward", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P])
+_sig("fcfs_backward_noalloc", [_P, _I, _I64, _I64, _I64, _I64, _P, _P, _I64, _P, _P, _P, _P])
 
 
 class fcfs_request(ctypes.Structure):
@@ -212,6 +214,16 @@ def fcfs_backward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, 
                   ws_ptr, ws_bytes, stream) -> int:
     return lib.fcfs_backward(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, dx_ptr,
                              dw_ptr, ws_ptr, ws_bytes, stream)
+
+
+FCFS_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def fcfs_backward_noalloc(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, dx_ptr, dw_ptr,
+                          stream) -> int:
+    """fcfs_backward with the library's fixed device workspace (no allocation)."""
+    return lib.fcfs_backward_noalloc(plan, dtype, n, c_in, h, w, x_ptr, weight_ptr, c_out, dy_ptr, dx_ptr,
+                                     dw_ptr, stream)
 
 
 def fcfs_server_create(device: int, mem_budget_bytes: int, max_slots: int) -> int:

@@ -598,20 +598,36 @@ static fcfs_status backward_checks(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n
   return FCFS_OK;
 }
 
-fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
-                                    int64_t h, int64_t w, int64_t c_out, size_t* bytes) {
+}  // extern "C"
+
+namespace fcfs {
+
+fcfs_status backward_workspace_need(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                                    int64_t w, int64_t c_out, bool need_dw, size_t* bytes) {
   int64_t ho = 0, wo = 0;
   if (!bytes) return FCFS_E_INVAL;
   *bytes = 0;
-  const bool learned = plan && (plan->method == FCFS_LEARNED_DW4 || plan->method == FCFS_LEARNED_MIX4);
-  fcfs_status st = backward_checks(plan, dtype, n, c_in, h, w, c_out, false, &ho, &wo);
+  fcfs_status st = backward_checks(plan, dtype, n, c_in, h, w, c_out, need_dw, &ho, &wo);
   if (st != FCFS_OK) return st;
   if (n == 0 || c_in == 0 || h == 0 || w == 0) return FCFS_OK;
   BwdArgs a;
   std::memset(&a, 0, sizeof(a));
   size_t off_w, off_p;
+  return plan_backward(plan, n, c_in, c_out, (int)h, (int)w, (int)ho, (int)wo, need_dw, &a, bytes, &off_w, &off_p);
+}
+
+}  // namespace fcfs
+
+extern "C" {
+
+fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
+                                    int64_t h, int64_t w, int64_t c_out, size_t* bytes) {
+  if (!bytes) return FCFS_E_INVAL;
+  *bytes = 0;
+  if (!plan) return FCFS_E_INVAL;
   // sized for the weight gradient too when the method has weights
-  return plan_backward(plan, n, c_in, c_out, (int)h, (int)w, (int)ho, (int)wo, learned, &a, bytes, &off_w, &off_p);
+  const bool learned = plan->method == FCFS_LEARNED_DW4 || plan->method == FCFS_LEARNED_MIX4;
+  return backward_workspace_need(plan, dtype, n, c_in, h, w, c_out, learned, bytes);
 }
 
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,

@@ -180,6 +180,11 @@ fcfs_status launch_backward_f16(const BwdArgs& a, bool learned, hipStream_t stre
 fcfs_status launch_backward_mix_bf16(const BwdArgs& a, hipStream_t stream);
 fcfs_status launch_backward_mix_f16(const BwdArgs& a, hipStream_t stream);
 
+// Workspace bytes fcfs_backward needs for these sizes, with or without the
+// weight gradient (argument errors as fcfs_backward's).
+fcfs_status backward_workspace_need(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
+                                    int64_t w, int64_t c_out, bool need_dw, size_t* bytes);
+
 // Forward kernel launchers, one per storage type (fwd_<dtype>.hip).
 fcfs_status launch_forward_f32(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);
 fcfs_status launch_forward_bf16(int method, const FwdArgs& a, const FwdGeom& g, hipStream_t stream);

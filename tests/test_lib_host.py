@@ -79,6 +79,24 @@ def test_forward_validation_needs_no_gpu():
     fc.fcfs_plan_destroy(dw)
 
 
+def test_noalloc_backward_validation_needs_no_gpu():
+    """Argument errors and sizes beyond the fixed device array are refused
+    before the array is looked up or anything is enqueued."""
+    assert fc.fcfs_backward_noalloc(None, 0, 1, 1, 8, 8, None, None, 1, 16, 16, None, None) == fc.E_INVAL
+    fixed = fc.fcfs_plan(3, 2, 2, 1)
+    # a weight gradient for a fixed method, a c_out mismatch
+    assert fc.fcfs_backward_noalloc(fixed, 0, 1, 1, 8, 8, 16, None, 1, 16, None, 16, None) == fc.E_INVAL
+    assert fc.fcfs_backward_noalloc(fixed, 0, 1, 2, 8, 8, None, None, 3, 16, 16, None, None) == fc.E_INVAL
+    # an empty problem needs no workspace and enqueues nothing
+    assert fc.fcfs_backward_noalloc(fixed, 0, 0, 1, 8, 8, None, None, 1, None, 16, None, None) == fc.OK
+    mix = fc.fcfs_plan(5, 4, 4, 0)
+    need = fc.fcfs_backward_workspace(mix, 1, 1, 128, 64, 64, 128)
+    assert need > fc.FCFS_NOALLOC_SCRATCH_BYTES
+    assert fc.fcfs_backward_noalloc(mix, 1, 1, 128, 64, 64, 16, 16, 128, 16, 16, 16, None) == fc.E_UNSUPPORTED
+    fc.fcfs_plan_destroy(fixed)
+    fc.fcfs_plan_destroy(mix)
+
+
 FRACS = [(1, 1), (3, 2), (2, 3), (5, 4), (4, 5), (3, 4), (1, 2), (2, 1), (7, 3), (6, 4), (2, 11),
          (27, 11), (8, 1), (1, 8), (32, 31), (31, 32)]
 
