@@ -86,6 +86,38 @@ def oracle_band(xplane, p, q, method, pad, m_lo, m_hi, grid="half", weight=None,
     return full[pr * (m_lo - c0): pr * (m_hi - c0)]
 
 
+def oracle_band_cond(xplane, p, q, method, pad, m_lo, m_hi):
+    """As oracle_band, with the band's conditioning S = sum |w||x| beside it."""
+    from math import gcd
+    g = gcd(p, q)
+    pr, qr = p // g, q // g
+    H = xplane.shape[0]
+    start = max(0, qr * (m_lo - 2))
+    end = min(H, qr * (m_hi + 2))
+    crop = np.asarray(xplane[start:end], dtype=np.float64)[None, None]
+    r = oracle.forward(crop, p, q, method, pad)[0, 0]
+    S = oracle.condition(crop, p, q, method, pad)[0, 0]
+    c0 = start // qr
+    sl = slice(pr * (m_lo - c0), pr * (m_hi - c0))
+    return r[sl], S[sl]
+
+
+def band_check(g, r, S, dtype, tol=ACC, method="", what=""):
+    """|g - r| <= u |r| + u_sub + tol * S on a band (nearest: bit-exact);
+    returns the largest |g - r| / S."""
+    if method == "nearest":
+        np.testing.assert_array_equal(g, r.astype(np.float32), err_msg="nearest must be a bit-exact copy " + what)
+        return 0.0
+    err = np.abs(np.asarray(g, np.float64) - r)
+    bound = UNIT[dtype] * np.abs(r) + UNIT_ABS[dtype] + tol * S + 1e-30
+    bad = err > bound
+    if bad.any():
+        i = tuple(np.argwhere(bad)[0])
+        raise AssertionError("%s: %d of %d outside tolerance; first at %s: gpu %r oracle %r S %r"
+                             % (what, int(bad.sum()), bad.size, i, float(g[i]), float(r[i]), float(S[i])))
+    return float((err / np.maximum(S, 1e-30)).max())
+
+
 def oracle_crop(x, p, q, method, pad, mh, mw, weight=None, cout=None):
     """Oracle outputs of cells mh = (lo, hi) x mw = (lo, hi) of every plane,
     computed from a crop of the input that holds every sample those cells
