@@ -69,6 +69,8 @@ def _load():
             lib.fcfs_oracle_backward.restype = I
             lib.fcfs_oracle_backward_absw.argtypes = lib.fcfs_oracle_backward.argtypes
             lib.fcfs_oracle_backward_absw.restype = I
+            lib.fcfs_oracle_set_threads.argtypes = [I]
+            lib.fcfs_oracle_set_threads.restype = None
             lib.fcfs_oracle_threads.argtypes = []
             lib.fcfs_oracle_threads.restype = I
             _lib = lib
@@ -175,3 +177,8 @@ def condition_backward(dy, x_shape, p, q, method="bilinear", pad="replicate", gr
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().fcfs_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Use n OpenMP threads in later calls (timing on one core and on all)."""
+    _load().fcfs_oracle_set_threads(int(n))

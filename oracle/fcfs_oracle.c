@@ -474,6 +474,16 @@ int fcfs_oracle_backward_absw(long rh, long sh, long rw, long sw, int method, in
   return o_backward(rh, sh, rw, sw, method, pad, grid, N, Cin, H, W, x, weight, Cout, dy, dx, dw, 1);
 }
 
+/* Threads later parallel regions use (for timing the oracle on one core). */
+void fcfs_oracle_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Number of OpenMP threads a parallel region uses (for reporting). */
 int fcfs_oracle_threads(void) {
 #ifdef _OPENMP
