@@ -47,6 +47,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_BF16_TFLOPS = 2500.0
+MFMA_PEAK_F32_TFLOPS = 157.3
 FRACS = [(3, 2), (2, 3), (5, 4), (4, 5)]
 METHODS = ["nearest", "bilinear", "bicubic"]
 PADS = ["zero", "reflect"]
@@ -90,7 +91,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-MIX_SOURCES = ("mix4_cl.h", "mix4_kernel.h", "mix4.hip", "bwd_mix.h", "bwd_mix.hip")
+MIX_SOURCES = ("mix4_cl.h", "mix4_kernel.h", "mix4.hip", "mix4_f32.hip", "bwd_mix.h", "bwd_mix.hip")
 
 
 def mix_source_hash() -> str:
@@ -110,7 +111,7 @@ def write_mfma(d):
     per = {}
     for r in _counter_rows(d, "MfmaUtil"):
         name = r["Kernel_Name"]
-        for key in ("mix4_cl_kernel", "mix4_kernel", "dx_mix", "dw_mix_partial", "dw_mix_reduce"):
+        for key in ("mix4_cl_kernel", "mix4_kernel", "mix4_f32_kernel", "dx_mix", "dw_mix_partial", "dw_mix_reduce"):
             if key in name:
                 per.setdefault(key, []).append(float(r["Counter_Value"]))
     for k, v in per.items():
@@ -248,6 +249,20 @@ def row_mix4(reps: int, backward: bool = True):
                                       "mfma_frac": round(flops / us / 1e6 / MFMA_PEAK_BF16_TFLOPS, 4),
                                       "mfma_util_counter_pct": counter("mix4_cl_kernel") or counter("mix4_kernel"),
                                       "Mpix_per_s": round(N * C * ho * wo / us, 1)}
+    # FP32 storage on the FP32 matrix cores, same layer
+    x32 = xb.float()
+    w32 = wm.float()
+    y32 = torch.empty((N, C, ho, wo), dtype=torch.float32, device=dev)
+
+    def runf(i=0):
+        st = fc.fcfs_forward(plm.handle, 0, N, C, H, W, x32.data_ptr(), w32.data_ptr(), C, y32.data_ptr(), sp)
+        assert st == 0
+    uf = _timeit(runf, max(2, reps // 4))
+    out["mix4_5_4_16x64x512_f32"] = {"us": round(uf, 2), "flop": flops, "TFLOPs": round(flops / uf / 1e6, 1),
+                                     "mfma_frac": round(flops / uf / 1e6 / MFMA_PEAK_F32_TFLOPS, 4),
+                                     "mfma_util_counter_pct": counter("mix4_f32_kernel"),
+                                     "Mpix_per_s": round(N * C * ho * wo / uf, 1)}
+    del x32, w32, y32
     if backward:
         dym = ym
         dxm = torch.empty_like(xb)

@@ -122,8 +122,9 @@ fcfs_status fcfs_output_size(fcfs_plan_t plan, int64_t h, int64_t w, int64_t* h_
  *            4x4 taps per channel and phase, tap (a, b) reading input row
  *            q*m_h + floor(u_h) - 1 + a and column q*m_w + floor(u_w) - 1 + b.
  *            LEARNED_MIX4: [p_h][p_w][c_out][c_in][4][4] in the storage type
- *            (BF16 or FP16; the layer runs on 16-bit MFMA with FP32
- *            accumulation), 16-byte aligned; same taps, summed over c_in.
+ *            (BF16 or FP16 run on the 16-bit matrix cores with FP32
+ *            accumulation, FP32 on the FP32 matrix cores), 16-byte aligned;
+ *            same taps, summed over c_in.
  *   c_out  : output channels; must equal c_in except for LEARNED_MIX4.
  *   y      : device, [n][c_out][h_out][w_out] of dtype; must not overlap x.
  *   stream : HIP stream the kernels are enqueued on (0 = the null stream).
@@ -131,9 +132,8 @@ fcfs_status fcfs_output_size(fcfs_plan_t plan, int64_t h, int64_t w, int64_t* h_
  * its pointers are not inspected.
  * Errors: FCFS_E_INVAL (negative sizes, null pointers, weight missing for a learned
  * method or given for a fixed one, c_out mismatch, a misaligned MIX4 weight),
- * FCFS_E_UNSUPPORTED (a per-plane size at or above 2^31 samples, LEARNED_MIX4
- * with FP32 storage, LEARNED_DW4 with more than 64 phases), FCFS_E_DEVICE
- * (launch failed). */
+ * FCFS_E_UNSUPPORTED (a per-plane size at or above 2^31 samples, LEARNED_DW4
+ * with more than 64 phases), FCFS_E_DEVICE (launch failed). */
 fcfs_status fcfs_forward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
                          int64_t w, const void* x, const void* weight, int64_t c_out, void* y,
                          hipStream_t stream);
@@ -205,7 +205,7 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
  *   LEARNED_MIX4 (16-bit storage): weight [p_h][p_w][c_out][c_in][4][4] in
  *        the storage type, 16-byte aligned; dx[c] sums over every output
  *        channel o too; dw is FP32 [p_h][p_w][c_out][c_in][4][4]. FP32
- *        storage returns FCFS_E_UNSUPPORTED, as for the forward.
+ *        storage returns FCFS_E_UNSUPPORTED (the forward has it).
  *   workspace / ws_bytes: device scratch of at least fcfs_backward_workspace
  *        bytes (NULL allowed when that is 0).
  * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small,

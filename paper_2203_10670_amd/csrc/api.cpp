@@ -307,11 +307,37 @@ static fcfs_status check_common(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   return FCFS_OK;
 }
 
-// Channel-mixing layer: 16-bit storage only, weights in the storage type.
+// Channel-mixing layer, FP32 storage: the largest group of at most 5 width
+// phases whose taps span at most 8 columns per cell.
+static fcfs_status forward_mix4_f32(fcfs_plan_t plan, const MixArgs& base, hipStream_t stream) {
+  MixArgs a = base;
+  const AxisTable& tw = plan->aw;
+  int G = std::min(5, tw.p), wspan = 0;
+  for (; G >= 1; --G) {
+    int spread = 0;
+    for (int j0 = 0; j0 < tw.p; j0 += G) {
+      const int j1 = std::min(tw.p, j0 + G) - 1;
+      spread = std::max(spread, tw.off[j1] - tw.off[j0]);
+    }
+    wspan = spread + 4;
+    if (wspan <= 8) break;
+  }
+  a.gsize = G;
+  a.groups = (tw.p + G - 1) / G;
+  a.wspan = wspan;
+  a.tiles_h = (a.Mh + 3) / 4;
+  a.tiles_w = (a.Mw + 15) / 16;
+  a.otiles = (a.Cout + 63) / 64;
+  const int64_t blocks = (int64_t)a.N * a.tiles_h * a.tiles_w * plan->ah.p * a.groups * a.otiles;
+  if (blocks >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
+  return launch_mix4_f32(a, stream);
+}
+
+// Channel-mixing layer: weights in the storage type; 16-bit storage on the
+// 16-bit matrix cores, FP32 storage on the FP32 ones.
 static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
                                 int64_t w, int64_t ho, int64_t wo, const void* x, const void* weight,
                                 int64_t c_out, void* y, hipStream_t stream) {
-  if (dtype == FCFS_F32) return FCFS_E_UNSUPPORTED;
   if ((reinterpret_cast<uintptr_t>(weight) & 15) != 0) return FCFS_E_INVAL;
   if (n > INT32_MAX || c_in > INT32_MAX || c_out > INT32_MAX) return FCFS_E_UNSUPPORTED;
   MixArgs a;
@@ -331,6 +357,7 @@ static fcfs_status forward_mix4(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
   a.pad = plan->pad;
   a.th = plan->ah;
   a.tw_tab = plan->aw;
+  if (dtype == FCFS_F32) return forward_mix4_f32(plan, a, stream);
   const int P = std::min(5, plan->aw.p);   // width phases per group
   a.gsize = P;
   a.groups = (plan->aw.p + P - 1) / P;

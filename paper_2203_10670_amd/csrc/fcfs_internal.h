@@ -172,6 +172,10 @@ fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int dtype, int64_t p
 
 // Channel-mixing launchers (mix4.hip); dtype FCFS_BF16 or FCFS_F16.
 fcfs_status launch_mix4(int dtype, const MixArgs& a, hipStream_t stream);
+// FP32 storage on the FP32 matrix cores (mix4_f32.hip): 64 cells (4 cell rows
+// of 16) x 64 outputs x a group of gsize width phases per workgroup, with
+// wspan <= 8 tap columns per cell.
+fcfs_status launch_mix4_f32(const MixArgs& a, hipStream_t stream);
 
 // Backward kernel launchers, one per storage type (bwd_<dtype>.hip).
 fcfs_status launch_backward_f32(const BwdArgs& a, bool learned, hipStream_t stream);

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2203_10670_amd", "csrc")
 OUT = os.path.join(HERE, "_build", "libfcfs_hostemu.so")
 SOURCES = ["api.cpp", "fwd_plan.cpp", "fwd_f32.hip", "fwd_bf16.hip", "fwd_f16.hip", "bwd_f32.hip", "bwd_bf16.hip", "bwd_f16.hip", "bwd_mix.hip",
-           "mix4.hip"]
+           "mix4.hip", "mix4_f32.hip"]
 CXX = "/opt/rocm/llvm/bin/clang++"   # host compile; knows __bf16, _Float16 and vector extensions
 
 

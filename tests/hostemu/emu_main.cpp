@@ -15,9 +15,13 @@ alignas(16) float smem[hostemu::kLdsFloats];
 namespace bwdmix {
 alignas(16) float smem[hostemu::kLdsFloats];
 }  // namespace bwdmix
+namespace mixf32 {
+alignas(16) float smem[hostemu::kLdsFloats];
+}  // namespace mixf32
 }  // namespace fcfs
 
 namespace hostemu {
-float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem, fcfs::mix::smem, fcfs::bwdmix::smem};
+float* const lds_arrays[] = {fcfs::fwd::smem, fcfs::bwd::smem, fcfs::mix::smem, fcfs::bwdmix::smem,
+                             fcfs::mixf32::smem};
 const int n_lds_arrays = sizeof(lds_arrays) / sizeof(lds_arrays[0]);
 }  // namespace hostemu

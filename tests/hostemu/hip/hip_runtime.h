@@ -99,10 +99,22 @@ inline uint32_t raw_buffer_load_b32(BufferRsrc r, int voff, int soff, int) {
   std::memcpy(&v, r.base + off, 4);
   return v;
 }
+inline uint16_t raw_buffer_load_b16(BufferRsrc r, int voff, int soff, int) {
+  if (voff < 0 || (int64_t)voff + 2 > r.records) return 0u;
+  const int64_t off = (int64_t)voff + soff;
+  if (soff < 0 || off + 2 > r.records) {
+    std::fprintf(stderr, "raw buffer load past the range: voff %d soff %d records %d\n", voff, soff, r.records);
+    std::abort();
+  }
+  uint16_t v;
+  std::memcpy(&v, r.base + off, 2);
+  return v;
+}
 }  // namespace hostemu
 typedef hostemu::BufferRsrc __amdgpu_buffer_rsrc_t;
 #define __builtin_amdgcn_make_buffer_rsrc(p, stride, num, flags) hostemu::make_buffer_rsrc(p, stride, num, flags)
 #define __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, aux) hostemu::raw_buffer_load_b32(r, voff, soff, aux)
+#define __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, aux) hostemu::raw_buffer_load_b16(r, voff, soff, aux)
 
 struct uint4 {
   unsigned x, y, z, w;
@@ -177,6 +189,28 @@ inline F4 mfma_16x16x32(V8 a, V8 b, F4 c) {
   return out;
 }
 }  // namespace hostemu
+// v_mfma_f32_16x16x4_f32: A lane l = row l%16, k = l/16 (one float); B lane
+// l = column l%16, same k; D as above.
+namespace hostemu {
+template <class F4>
+inline F4 mfma_16x16x4_f32(float a, float b, F4 c) {
+  const int l = (int)(tid_.x & 63);
+  WaveScratch* s = wave_scratch_;
+  s->a[l][0] = a;
+  s->b[l][0] = b;
+  wave_bar_->arrive_and_wait();
+  F4 out = c;
+  for (int i = 0; i < 4; ++i) {
+    const int m = 4 * (l / 16) + i, n = l % 16;
+    float acc = 0.f;
+    for (int k = 0; k < 4; ++k) acc += s->a[m + 16 * k][0] * s->b[n + 16 * k][0];
+    out[i] += acc;
+  }
+  wave_bar_->arrive_and_wait();
+  return out;
+}
+}  // namespace hostemu
+#define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) hostemu::mfma_16x16x4_f32(a, b, c)
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) hostemu::mfma_16x16x32(a, b, c)
 #define __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, x, y, z) hostemu::mfma_16x16x32(a, b, c)
 

@@ -98,7 +98,10 @@ def test_channel_mixing_backward():
                                           (2, 3, "replicate", "bf16", [1, 2, 11, 300], 3),
                                           (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2),
                                           # two column blocks, both columns of a thread live in the first
-                                          (5, 4, "reflect", "bf16", [1, 3, 5, 700], 6)]:
+                                          (5, 4, "reflect", "bf16", [1, 3, 5, 700], 6),
+                                          # 8 width phases and several output tiles; q = 7
+                                          (8, 3, "zero", "bf16", [1, 4, 10, 100], 70),
+                                          (4, 7, "reflect", "f16", [1, 9, 17, 270], 20)]:
         cases.append({"mode": "bwd", "p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": shape,
                       "cout": cout})
     _run(cases)
@@ -161,6 +164,16 @@ def test_channel_mixing_mfma():
     # a second width-phase group that starts at an odd column (and has one phase)
     cases.append({"p": 6, "q": 5, "method": "mix4", "pad": "reflect", "dtype": "bf16", "shape": [1, 9, 12, 170],
                   "cout": 3})
-    cases.append({"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 2, 8, 8],
-                  "cout": 2, "expect_status": 2})
     _run(cases)
+
+
+def test_channel_mixing_fp32():
+    # FP32 storage on the FP32 matrix cores: ragged cell tiles, two output
+    # tiles, large q (only the tapped columns staged), several phase groups
+    _run([{"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 2, 8, 8], "cout": 2},
+          {"p": 5, "q": 4, "method": "mix4", "pad": "reflect", "dtype": "f32", "shape": [2, 6, 13, 70],
+           "cout": 70},
+          {"p": 2, "q": 7, "method": "mix4", "pad": "reflect", "dtype": "f32", "shape": [1, 5, 30, 60], "cout": 3},
+          {"p": 9, "q": 8, "method": "mix4", "pad": "replicate", "dtype": "f32", "shape": [1, 3, 20, 75],
+           "cout": 4},
+          {"p": 3, "q": 2, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 9, 7, 35], "cout": 17}])

@@ -90,9 +90,9 @@ def test_noalloc_backward_validation_needs_no_gpu():
     # an empty problem needs no workspace and enqueues nothing
     assert fc.fcfs_backward_noalloc(fixed, 0, 0, 1, 8, 8, None, None, 1, None, 16, None, None) == fc.OK
     mix = fc.fcfs_plan(5, 4, 4, 0)
-    need = fc.fcfs_backward_workspace(mix, 1, 1, 128, 64, 64, 128)
+    need = fc.fcfs_backward_workspace(mix, 1, 1, 256, 64, 64, 256)
     assert need > fc.FCFS_NOALLOC_SCRATCH_BYTES
-    assert fc.fcfs_backward_noalloc(mix, 1, 1, 128, 64, 64, 16, 16, 128, 16, 16, 16, None) == fc.E_UNSUPPORTED
+    assert fc.fcfs_backward_noalloc(mix, 1, 1, 256, 64, 64, 16, 16, 256, 16, 16, 16, None) == fc.E_UNSUPPORTED
     fc.fcfs_plan_destroy(fixed)
     fc.fcfs_plan_destroy(mix)
 

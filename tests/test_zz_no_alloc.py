@@ -100,7 +100,7 @@ def test_noalloc_refuses_a_workspace_above_its_array():
     even a launch would stay in bounds)."""
     import torch
     import paper_2203_10670_amd as fc
-    n, c, h, w, cout = 1, 128, 64, 64, 128
+    n, c, h, w, cout = 1, 256, 64, 64, 256
     pl = fc.Plan(5, 4, "mix4", "zero")
     need = fc.fcfs_backward_workspace(pl.handle, 1, n, c, h, w, cout)
     assert need > fc.FCFS_NOALLOC_SCRATCH_BYTES
