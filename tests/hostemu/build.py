@@ -6,7 +6,10 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2203_10670_amd", "csrc")
-OUT = os.path.join(HERE, "_build", "libfcfs_hostemu.so")
+# extra -D flags (compile-time tuning switches of the kernels) build a separate library
+EXTRA = os.environ.get("FCFS_HOSTEMU_DEFINES", "").split()
+OUT = os.path.join(HERE, "_build", "libfcfs_hostemu%s.so" % ("_" + "_".join(d.lstrip("-D") for d in EXTRA) if EXTRA
+                                                            else ""))
 SOURCES = ["api.cpp", "fwd_plan.cpp", "fwd_f32.hip", "fwd_bf16.hip", "fwd_f16.hip", "bwd_f32.hip", "bwd_bf16.hip", "bwd_f16.hip", "bwd_mix.hip",
            "mix4.hip", "mix4_f32.hip"]
 CXX = "/opt/rocm/llvm/bin/clang++"   # host compile; knows __bf16, _Float16 and vector extensions
@@ -21,11 +24,12 @@ def build(sanitize: bool = True) -> str:
     if os.path.exists(OUT) and os.path.getmtime(OUT) >= newest:
         return OUT
     flags = ["-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-w",
-             "-I", HERE, "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+             "-I", HERE, "-I", os.path.join(ROOT, "include"), "-I", CSRC] + EXTRA
     if sanitize:
         flags += ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
     from concurrent.futures import ThreadPoolExecutor
-    objdir = os.path.join(os.path.dirname(OUT), "obj")
+    objdir = os.path.join(os.path.dirname(OUT), "obj" + ("_" + "_".join(d.lstrip("-D") for d in EXTRA) if EXTRA
+                                                         else ""))
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
