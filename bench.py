@@ -415,7 +415,7 @@ def measure_quality():
     return rows
 
 
-def measure_serving(count: int, rhos=(0.25, 0.5, 0.8, 0.95)):
+def measure_serving(count: int, rhos=(0.25, 0.5, 0.8, 0.95), chunk_waves=None):
     """The serving loop on a seeded request stream: C=3, H and W uniform in
     64..2048, p and q uniform in 1..8, method uniform, FP32 or BF16 by seed,
     inputs generated on the device from each request's seed, outputs freed on
@@ -428,6 +428,8 @@ def measure_serving(count: int, rhos=(0.25, 0.5, 0.8, 0.95)):
     reqs = [fc.fcfs_request(r.p, r.q, r.method, r.pad, r.dtype, 1, r.c, r.h, r.w, None, r.seed, None) for r in meta]
     srv = fc.Server(0, 64 << 30, 256)
     fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_DISCARD_OUTPUTS, 1)
+    if chunk_waves is not None:
+        fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_CHUNK_WAVES, chunk_waves)
 
     def run(arrivals, max_batch, subset=None):
         rq = reqs if subset is None else reqs[:subset]
@@ -563,6 +565,20 @@ def summarize(d):
             short = name if len(name) <= 100 else name[:97] + "..."
             print("%-100s %6s %12.2f %12.1f %6.2f" % (short, r["Calls"], float(r["AverageNs"]) / 1e3,
                                                        float(r["TotalDurationNs"]) / 1e3, float(r["Percentage"])))
+    # overlap of consecutive batched serving launches (two streams): a launch
+    # that starts before the previous one ends ran beside it
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(fh)
+                        if "fwd_batch_kernel" in r["Kernel_Name"])
+        if len(ev) < 2:
+            continue
+        over = [(a[1] - b[0]) for a, b in zip(ev, ev[1:]) if b[0] < a[1]]
+        busy = sum(e - s_ for s_, e in ev)
+        print("# serving overlap (%s): %d batched launches, %d start before the previous one ends; "
+              "overlapped time %.1f us of %.1f us of kernel time (median overlap %.1f us)"
+              % (os.path.relpath(f, d), len(ev), len(over), sum(over) / 1e3, busy / 1e3,
+                 sorted(over)[len(over) // 2] / 1e3 if over else 0.0))
     ctr = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     for f in ctr:
         print("# counters:", os.path.relpath(f, d))
@@ -682,6 +698,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true",
                     help="profiling only: skip the step sweep and print the rows' JSON (not a benchmark line)")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests of the serving run (0: skip)")
+    ap.add_argument("--serve-chunk-waves", type=int, default=None,
+                    help="most waves of one request per batch (0: no chunking; default: the server's)")
     ap.add_argument("--filter", default="", help="only cases whose name contains this text")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -737,7 +755,7 @@ def main():
         if "quality" in rows_sel:
             rows["quality_vs_framework_resize"] = measure_quality()
         if "serving" in rows_sel and args.serve_requests > 0:
-            rows["serving"] = measure_serving(args.serve_requests)
+            rows["serving"] = measure_serving(args.serve_requests, chunk_waves=args.serve_chunk_waves)
         return rows
 
     if args.no_sweep:

@@ -247,9 +247,10 @@ fcfs_status fcfs_backward_noalloc(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n,
  * launches one batched forward kernel per scheduling tick covering every
  * newly admitted request (mixed sizes, factors, methods and storage types),
  * alternating two HIP streams so that requests arriving while a batch runs
- * are launched next to it. Buffers stay on the device. A completion thread
- * timestamps finished batches. Results equal fcfs_forward's bit for bit (the
- * same per-wave code runs). */
+ * are launched next to it. A request with more waves than the chunk size
+ * (FCFS_SERVER_CHUNK_WAVES) runs as chunks over consecutive batches. Buffers
+ * stay on the device. A completion thread timestamps finished batches.
+ * Results equal fcfs_forward's bit for bit (the same per-wave code runs). */
 
 typedef struct fcfs_server_* fcfs_server_t;
 
@@ -289,7 +290,10 @@ typedef struct {
 fcfs_status fcfs_server_create(int device, size_t mem_budget_bytes, int max_slots, fcfs_server_t* out);
 
 /* Queue a request; *ticket identifies it. Argument errors are returned here
- * and queue nothing. FCFS_E_AGAIN when the pending queue is full. */
+ * and queue nothing: FCFS_E_INVAL (method, storage type, sizes), and
+ * FCFS_E_UNSUPPORTED for a plane of 2^31 samples or more, a reduced factor
+ * above 32 or sizes whose byte counts overflow. FCFS_E_AGAIN when the
+ * pending queue is full. */
 fcfs_status fcfs_submit(fcfs_server_t server, const fcfs_request* req, uint64_t* ticket);
 
 /* FCFS_OK with *out filled when the request is finished (out->status holds
@@ -316,11 +320,19 @@ fcfs_status fcfs_server_stats(fcfs_server_t server, double* p50_us, double* p99_
  * `value` batches fail as if their launch had failed (nothing is launched). */
 fcfs_status fcfs_server_debug(fcfs_server_t server, int hook, int64_t value);
 
-/* Server options. FCFS_SERVER_MAX_BATCH: most requests per batched launch
- * (0 = no limit; 1 = one launch per request, for comparisons).
+/* Server options. FCFS_SERVER_MAX_BATCH: most newly admitted requests per
+ * batched launch (0 = no limit; 1 = one launch per request, for comparisons).
  * FCFS_SERVER_DISCARD_OUTPUTS: 1 = free server-owned outputs as soon as a
- * request finishes (its result then has y = NULL; for load tests). */
-typedef enum { FCFS_SERVER_MAX_BATCH = 1, FCFS_SERVER_DISCARD_OUTPUTS = 2 } fcfs_server_option;
+ * request finishes (its result then has y = NULL; for load tests).
+ * FCFS_SERVER_CHUNK_WAVES: most waves (64 output columns by a band of rows
+ * each) of one request per batch, default 16384: a larger request runs as
+ * chunks in consecutive batches, next to the requests admitted meanwhile
+ * (0 = no chunking). */
+typedef enum {
+  FCFS_SERVER_MAX_BATCH = 1,
+  FCFS_SERVER_DISCARD_OUTPUTS = 2,
+  FCFS_SERVER_CHUNK_WAVES = 3
+} fcfs_server_option;
 fcfs_status fcfs_server_config(fcfs_server_t server, int option, int64_t value);
 
 /* Submit `count` requests from the calling thread, request i when

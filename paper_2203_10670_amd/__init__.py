@@ -39,7 +39,7 @@ GRIDS = {"half": 0, "paper": 1, "asym": 2}
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 OK, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_AGAIN, E_PENDING, E_CANCELLED = range(8)
-FCFS_SERVER_MAX_BATCH, FCFS_SERVER_DISCARD_OUTPUTS = 1, 2
+FCFS_SERVER_MAX_BATCH, FCFS_SERVER_DISCARD_OUTPUTS, FCFS_SERVER_CHUNK_WAVES = 1, 2, 3
 
 
 class FcfsError(RuntimeError):

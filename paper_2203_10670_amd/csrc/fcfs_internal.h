@@ -136,11 +136,14 @@ struct MixArgs {
 };
 
 // ---------------------------------------------------------------- serving
-// One request of a batched launch (in device memory).
+// One request of a batched launch (in device memory): waves wave_begin ..
+// wave_begin + (its share of the batch) - 1 of the request's forward, so a
+// large request runs as chunks spread over several batches.
 struct BatchDesc {
   FwdArgs args;
+  int64_t wave_begin;
   int variant;      // forward instance: dtype (0 f32, 1 bf16) * 6 + tap index (0: 1, 1: 2, 2: 4) * 2 + (kc == 4 ? 0 : 1)
-  int pad_[3];
+  int pad_;
 };
 struct BatchArgs {
   const BatchDesc* desc;
@@ -165,10 +168,11 @@ struct GenArgs {
 constexpr int kGenPerBlock = 256 * 16;   // elements per generator block
 
 fcfs_status launch_forward_batch(const BatchArgs& b, hipStream_t stream);
-fcfs_status launch_generate(const GenArgs& g, hipStream_t stream);
 // Launch geometry for a batched request (restricted to the batched kernel's instances).
 fcfs_status plan_forward_geom_batch(const fcfs_plan_* plan, int dtype, int64_t planes, int h, int w, int ho,
                                     int wo, FwdGeom* g);
+fcfs_status launch_generate(const GenArgs& g, hipStream_t stream);
+
 
 // Channel-mixing launchers (mix4.hip); dtype FCFS_BF16 or FCFS_F16.
 fcfs_status launch_mix4(int dtype, const MixArgs& a, hipStream_t stream);

@@ -1,12 +1,16 @@
 // Serving loop of libfcfs: continuous batching of rescale requests on one GPU.
 //
 // Threads. Clients call fcfs_submit from any thread (requests go to a FIFO).
-// The scheduler thread admits requests from the head of the FIFO while
-// request slots and the device arena allow, then launches one batch: a
-// generator launch for the admitted requests whose input it must create, the
-// descriptor upload and one batched forward launch, on one of two streams in
-// turn. The completion thread waits for each batch's event in launch order,
-// timestamps its requests and frees their arena inputs and slots.
+// The scheduler thread builds one batch per tick: first the next chunk of
+// every admitted request that still has waves to launch, then new requests
+// admitted from the head of the FIFO while request slots and the device arena
+// allow. A batch is a generator launch for the newly admitted requests whose
+// input it must create, the descriptor upload and one batched forward launch,
+// on one of two streams in turn. A request larger than the chunk size (in
+// waves) runs as chunks over several batches, so requests that arrive behind
+// it start in the next tick instead of after all of it. The completion thread
+// waits for each batch's event in launch order, timestamps the requests whose
+// last chunk it held and frees their arena inputs and slots.
 //
 // Memory. The arena is one device allocation made at creation; a first-fit
 // free list (offsets, 256-byte granules, neighbours merged on free) hands out
@@ -36,6 +40,7 @@ namespace {
 
 constexpr size_t kGranule = 256;
 constexpr size_t kMaxPending = 1 << 16;
+constexpr int64_t kDefaultChunkWaves = 16384;   // about five times the waves the GPU holds at once
 
 size_t round_up(size_t b) { return (b + kGranule - 1) / kGranule * kGranule; }
 
@@ -92,6 +97,12 @@ struct Ticket {
   int state = kPending;
   fcfs_status status = FCFS_OK;
   fcfs_plan_t plan = nullptr;
+  FwdGeom geom;                                // launch geometry of the batched kernel
+  int variant = 0;
+  int64_t waves_launched = 0;                  // waves of the forward in launched batches
+  int chunks_inflight = 0;                     // launched batches holding a chunk, not yet complete
+  bool failed = false;                         // a batch holding one of its chunks failed
+  int gen_stream = -1;                         // stream of the batch that generated the input
   int64_t ho = 0, wo = 0;
   size_t x_bytes = 0, y_bytes = 0;
   size_t x_off = SIZE_MAX, y_off = SIZE_MAX;   // arena offsets when server-owned
@@ -99,6 +110,14 @@ struct Ticket {
   void* y = nullptr;
   uint64_t alg_bytes = 0;                      // input rows read + output
   double t_arrive = 0, t_start = 0, t_done = 0;
+};
+
+// A chunk of a request in the batch being built: forward instance, ticket,
+// first wave and number of waves.
+struct Chunk {
+  int variant;
+  uint64_t id;
+  int64_t begin, n;
 };
 
 struct Batch {
@@ -139,6 +158,9 @@ struct fcfs_server_ {
   std::condition_variable cv_done;     // waiters: a request finished
   std::condition_variable cv_batch;    // completion thread: a batch was launched
   std::deque<uint64_t> fifo;           // pending tickets in arrival order
+  std::deque<uint64_t> active;         // admitted tickets with waves still to launch, in admission order
+  std::vector<fcfs::Chunk> chunk_scratch;   // the chunks of the batch being built
+  int64_t chunk_waves = fcfs::kDefaultChunkWaves;   // most waves of one request per batch (0: no limit)
   std::unordered_map<uint64_t, fcfs::Ticket> tickets;
   std::deque<fcfs::Batch> inflight;
   std::map<uint64_t, fcfs_plan_t> plans;   // plan cache by (p, q, method, pad)
@@ -172,19 +194,31 @@ uint64_t plan_key(const fcfs_request& r) {
   return ((uint64_t)r.p << 40) | ((uint64_t)r.q << 20) | ((uint64_t)r.method << 8) | (uint64_t)r.pad;
 }
 
-// Input rows some tap reads (height axis) times the row bytes, plus the output.
+// Input rows some tap reads (height axis) times the row bytes, plus the
+// output. Row r is read when r = q m + d for a tap offset d = off[j] + k and a
+// cell m < cells; the offsets are few, so each row is checked against them
+// (no allocation; called outside the server lock).
 uint64_t algorithmic_bytes(const fcfs_plan_* pl, const Ticket& t, size_t es) {
   const AxisTable& a = pl->ah;
   const int64_t h = t.req.h, cells = t.ho / a.p;
-  std::vector<char> hit((size_t)h, 0);
-  for (int64_t m = 0; m < cells; ++m)
-    for (int j = 0; j < a.p; ++j)
-      for (int k = 0; k < a.T; ++k) {
-        const int64_t r = a.q * m + a.off[j] + k;
-        if (r >= 0 && r < h) hit[(size_t)r] = 1;
-      }
+  int d[kMaxFactor * 4];
+  int nd = 0;
+  for (int j = 0; j < a.p; ++j)
+    for (int k = 0; k < a.T; ++k) {
+      const int v = a.off[j] + k;
+      bool seen = false;
+      for (int i = 0; i < nd; ++i) seen = seen || d[i] == v;
+      if (!seen) d[nd++] = v;
+    }
   int64_t rows = 0;
-  for (char c : hit) rows += c;
+  for (int64_t r = 0; r < h; ++r) {
+    bool hit = false;
+    for (int i = 0; i < nd && !hit; ++i) {
+      const int64_t e = r - d[i];
+      hit = e >= 0 && e % a.q == 0 && e / a.q < cells;
+    }
+    rows += hit;
+  }
   return (uint64_t)(t.req.n * t.req.c) * (uint64_t)(rows * t.req.w + t.ho * t.wo) * es;
 }
 
@@ -240,17 +274,43 @@ bool reserve(fcfs_server_* s, Ticket& t) {
   return true;
 }
 
+// Forward arguments of a request (lock held or not: reads the ticket only).
+void fill_desc(const Ticket& t, BatchDesc& d) {
+  std::memset(&d, 0, sizeof(d));
+  FwdArgs& a = d.args;
+  a.x = t.x;
+  a.y = t.y;
+  a.weight = nullptr;
+  a.planes = t.req.n * t.req.c;
+  a.C = (int)t.req.c;
+  a.H = (int)t.req.h;
+  a.W = (int)t.req.w;
+  a.Ho = (int)t.ho;
+  a.Wo = (int)t.wo;
+  a.Mh = (int)(t.ho / t.plan->ah.p);
+  a.pad = t.plan->pad;
+  a.th = t.plan->ah;
+  a.tw_tab = t.plan->aw;
+  fill_emit(t.plan->ah, a.emit);
+  a.tw = t.geom.tw;
+  a.strips = t.geom.strips;
+  a.band_cells = t.geom.band_cells;
+  a.bands = t.geom.bands;
+  a.waves = t.geom.waves;
+  d.variant = t.variant;
+}
+
 void scheduler_loop(fcfs_server_* s) {
   hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     StreamBufs& sb = s->sb[s->next_stream];
     s->cv_sched.wait(lk, [&] {
-      return s->stop || (!s->fifo.empty() && s->slots_used < s->max_slots && !sb.busy);
+      return (s->stop && s->active.empty()) ||
+             (!sb.busy && (!s->active.empty() || (!s->fifo.empty() && s->slots_used < s->max_slots)));
     });
-    if (s->stop && s->fifo.empty()) break;
     if (s->stop) {
-      // cancel whatever never started
+      // cancel whatever was never admitted; admitted requests run to the end
       const double now = s->now_us();
       while (!s->fifo.empty()) {
         Ticket& t = s->tickets[s->fifo.front()];
@@ -258,15 +318,38 @@ void scheduler_loop(fcfs_server_* s) {
         finish(s, t, FCFS_E_CANCELLED, now);
       }
       s->cv_done.notify_all();
-      break;
+      if (s->active.empty()) break;
+      if (sb.busy) continue;
     }
-    // admit from the head of the FIFO
     Batch batch;
     batch.stream = s->next_stream;
     int ngen = 0;
     int64_t waves = 0, gblocks = 0;
+    bool wait_other = false;   // a continued chunk reads an input generated on the other stream
     const double now = s->now_us();
-    while (!s->fifo.empty() && s->slots_used < s->max_slots &&
+    std::vector<Chunk>& chunks = s->chunk_scratch;
+    chunks.clear();
+    auto add_chunk = [&](uint64_t id, Ticket& t) {
+      const int64_t left = t.geom.waves - t.waves_launched;
+      const int64_t n = s->chunk_waves > 0 ? std::min(left, s->chunk_waves) : left;
+      chunks.push_back(Chunk{t.variant, id, t.waves_launched, n});
+      t.waves_launched += n;
+      ++t.chunks_inflight;
+      batch.tickets.push_back(id);
+    };
+    // continue the admitted requests that still have waves to launch
+    const size_t nactive = s->active.size();
+    for (size_t k = 0; k < nactive; ++k) {
+      const uint64_t id = s->active.front();
+      s->active.pop_front();
+      Ticket& t = s->tickets[id];
+      if (t.failed) continue;   // an earlier chunk failed: launch nothing more
+      if (t.gen_stream >= 0 && t.gen_stream != batch.stream) wait_other = true;
+      add_chunk(id, t);
+      if (t.waves_launched < t.geom.waves) s->active.push_back(id);
+    }
+    // admit from the head of the FIFO
+    while (!s->stop && !s->fifo.empty() && s->slots_used < s->max_slots &&
            (s->max_batch == 0 || (int)batch.tickets.size() < s->max_batch)) {
       const uint64_t id = s->fifo.front();
       Ticket& t = s->tickets[id];
@@ -283,35 +366,6 @@ void scheduler_loop(fcfs_server_* s) {
       t.state = kAdmitted;
       t.t_start = now;
       ++s->slots_used;
-      // descriptor
-      const int i = (int)batch.tickets.size();
-      BatchDesc& d = sb.h_desc[i];
-      std::memset(&d, 0, sizeof(d));
-      FwdArgs& a = d.args;
-      a.x = t.x;
-      a.y = t.y;
-      a.weight = nullptr;
-      a.planes = t.req.n * t.req.c;
-      a.C = (int)t.req.c;
-      a.H = (int)t.req.h;
-      a.W = (int)t.req.w;
-      a.Ho = (int)t.ho;
-      a.Wo = (int)t.wo;
-      a.Mh = (int)(t.ho / t.plan->ah.p);
-      a.pad = t.plan->pad;
-      a.th = t.plan->ah;
-      a.tw_tab = t.plan->aw;
-      fill_emit(t.plan->ah, a.emit);
-      FwdGeom g;
-      plan_forward_geom_batch(t.plan, t.req.dtype, a.planes, a.H, a.W, a.Ho, a.Wo, &g);
-      a.tw = g.tw;
-      a.strips = g.strips;
-      a.band_cells = g.band_cells;
-      a.bands = g.bands;
-      a.waves = g.waves;
-      d.variant = variant_of(t.req.dtype, t.plan->ah.T, g.kc);
-      sb.h_wave[i] = waves;
-      waves += g.waves;
       if (!t.req.x) {
         GenDesc& gd = sb.h_gen[ngen];
         gd.x = t.x;
@@ -321,8 +375,10 @@ void scheduler_loop(fcfs_server_* s) {
         sb.h_gblk[ngen] = gblocks;
         gblocks += (gd.count + kGenPerBlock - 1) / kGenPerBlock;
         ++ngen;
+        t.gen_stream = batch.stream;
       }
-      batch.tickets.push_back(id);
+      add_chunk(id, t);
+      if (t.waves_launched < t.geom.waves) s->active.push_back(id);
     }
     if (batch.tickets.empty()) {
       // the head request waits for arena space: sleep until a completion or a
@@ -331,7 +387,17 @@ void scheduler_loop(fcfs_server_* s) {
       s->cv_sched.wait(lk, [&] { return s->stop || s->frees != seen || s->fifo.empty(); });
       continue;
     }
-    const int nreq = (int)batch.tickets.size();
+    // the descriptors of the batch's chunks (one launch covers them all: the
+    // waves of different requests run side by side)
+    const int nreq = (int)chunks.size();
+    for (int i = 0; i < nreq; ++i) {
+      const Chunk& c = chunks[(size_t)i];
+      BatchDesc& d = sb.h_desc[i];
+      fill_desc(s->tickets[c.id], d);
+      d.wave_begin = c.begin;
+      sb.h_wave[i] = waves;
+      waves += c.n;
+    }
     sb.h_wave[nreq] = waves;
     sb.h_gblk[ngen] = gblocks;
     bool fail = false;
@@ -340,11 +406,15 @@ void scheduler_loop(fcfs_server_* s) {
       fail = true;
     }
     // launch (outside the lock: the upload and launches do not touch shared state)
+    hipEvent_t other_last = s->sb[batch.stream ^ 1].last;
     sb.busy = true;
     s->next_stream ^= 1;
     lk.unlock();
     hipStream_t st = sb.stream;
     bool ok = !fail;
+    // inputs generated by a batch on the other stream must be complete before
+    // their later chunks run here (earlier batches of this stream are ordered)
+    if (ok && wait_other) ok = hipStreamWaitEvent(st, other_last, 0) == hipSuccess;
     if (ok && ngen > 0) {
       ok = hipMemcpyAsync(sb.d_gen, sb.h_gen, sizeof(GenDesc) * ngen, hipMemcpyHostToDevice, st) == hipSuccess &&
            hipMemcpyAsync(sb.d_gblk, sb.h_gblk, sizeof(int64_t) * (ngen + 1), hipMemcpyHostToDevice, st) ==
@@ -386,11 +456,20 @@ void completion_loop(fcfs_server_* s) {
     Batch done = std::move(s->inflight.front());
     s->inflight.pop_front();
     const double when = s->now_us();
-    const fcfs_status st = (done.failed || !dev_ok) ? FCFS_E_DEVICE : FCFS_OK;
+    const bool bad = done.failed || !dev_ok;
     for (uint64_t id : done.tickets) {
       Ticket& t = s->tickets[id];
-      finish(s, t, st, when);
-      --s->slots_used;
+      --t.chunks_inflight;
+      if (bad) t.failed = true;
+      // a request is done when its last chunk's batch completes
+      if (t.chunks_inflight == 0 && (t.waves_launched >= t.geom.waves || t.failed)) {
+        if (t.waves_launched < t.geom.waves) {   // failed early: launch none of the rest
+          auto it = std::find(s->active.begin(), s->active.end(), id);
+          if (it != s->active.end()) s->active.erase(it);
+        }
+        finish(s, t, t.failed ? FCFS_E_DEVICE : FCFS_OK, when);
+        --s->slots_used;
+      }
     }
     s->sb[done.stream].busy = false;
     ++s->frees;
@@ -463,6 +542,7 @@ fcfs_status fcfs_server_create(int device, size_t mem_budget_bytes, int max_slot
     ok = ok && hipMalloc(reinterpret_cast<void**>(&b.d_gen), sizeof(GenDesc) * max_slots) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&b.d_gblk), sizeof(int64_t) * (max_slots + 1)) == hipSuccess;
   }
+  s->chunk_scratch.reserve((size_t)max_slots);
   if (!ok) {
     for (auto& b : s->sb) free_stream_bufs(b);
     hipFree(s->arena_base);
@@ -482,25 +562,40 @@ fcfs_status fcfs_submit(fcfs_server_t s, const fcfs_request* r, uint64_t* ticket
   if (r->n < 1 || r->c < 1 || r->h < 1 || r->w < 1) return FCFS_E_INVAL;
   Ticket t;
   t.req = *r;
+  {
+    // the plan (cached per factor, method and padding; plans live until the
+    // server is destroyed, so the pointer stays valid without the lock)
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return FCFS_E_INVAL;
+    const uint64_t key = plan_key(*r);
+    auto it = s->plans.find(key);
+    if (it == s->plans.end()) {
+      fcfs_plan_t pl = nullptr;
+      fcfs_status st = fcfs_plan(r->p, r->q, r->method, r->pad, &pl);
+      if (st != FCFS_OK) return st;
+      it = s->plans.emplace(key, pl).first;
+    }
+    t.plan = it->second;
+  }
+  // sizes, launch geometry and byte count, outside the lock
+  fcfs_output_size(t.plan, r->h, r->w, &t.ho, &t.wo);
+  const size_t es = elem_size(r->dtype);
+  if (r->h >= (1LL << 31) || r->w >= (1LL << 31) || t.ho >= (1LL << 31) || t.wo >= (1LL << 31))
+    return FCFS_E_UNSUPPORTED;
+  const int64_t in_plane = r->h * r->w, out_plane = t.ho * t.wo;
+  if (in_plane >= (1LL << 31) || out_plane >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
+  const int64_t planes_max = INT64_MAX / 4 / std::max(in_plane, out_plane);   // bytes stay below 2^63
+  if (r->n > planes_max || r->c > planes_max / r->n) return FCFS_E_UNSUPPORTED;
+  t.x_bytes = (size_t)(r->n * r->c * in_plane) * es;
+  t.y_bytes = (size_t)(r->n * r->c * out_plane) * es;
+  fcfs_status gst = plan_forward_geom_batch(t.plan, r->dtype, r->n * r->c, (int)r->h, (int)r->w, (int)t.ho,
+                                            (int)t.wo, &t.geom);
+  if (gst != FCFS_OK) return gst;
+  t.variant = variant_of(r->dtype, t.plan->ah.T, t.geom.kc);
+  t.alg_bytes = algorithmic_bytes(t.plan, t, es);
   std::unique_lock<std::mutex> lk(s->mu);
   if (s->stop) return FCFS_E_INVAL;
   if (s->fifo.size() >= kMaxPending) return FCFS_E_AGAIN;
-  const uint64_t key = plan_key(*r);
-  auto it = s->plans.find(key);
-  if (it == s->plans.end()) {
-    fcfs_plan_t pl = nullptr;
-    fcfs_status st = fcfs_plan(r->p, r->q, r->method, r->pad, &pl);
-    if (st != FCFS_OK) return st;
-    it = s->plans.emplace(key, pl).first;
-  }
-  t.plan = it->second;
-  fcfs_output_size(t.plan, r->h, r->w, &t.ho, &t.wo);
-  const int64_t in_plane = r->h * r->w, out_plane = t.ho * t.wo;
-  if (in_plane >= (1LL << 31) || out_plane >= (1LL << 31)) return FCFS_E_UNSUPPORTED;
-  const size_t es = elem_size(r->dtype);
-  t.x_bytes = (size_t)(r->n * r->c * in_plane) * es;
-  t.y_bytes = (size_t)(r->n * r->c * out_plane) * es;
-  t.alg_bytes = algorithmic_bytes(t.plan, t, es);
   t.t_arrive = s->now_us();
   const uint64_t id = s->next_ticket++;
   s->tickets.emplace(id, std::move(t));
@@ -579,6 +674,7 @@ fcfs_status fcfs_server_config(fcfs_server_t s, int option, int64_t value) {
   std::lock_guard<std::mutex> lk(s->mu);
   if (option == FCFS_SERVER_MAX_BATCH) s->max_batch = (int)std::min<int64_t>(value, 1 << 30);
   else if (option == FCFS_SERVER_DISCARD_OUTPUTS) s->discard_outputs = value != 0;
+  else if (option == FCFS_SERVER_CHUNK_WAVES) s->chunk_waves = value;
   else return FCFS_E_INVAL;
   s->cv_sched.notify_all();
   return FCFS_OK;

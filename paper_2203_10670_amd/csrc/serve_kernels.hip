@@ -8,7 +8,8 @@ namespace serve {
 using fwd::fwd_wave;
 
 // Wave w of the batch finds its request r (wave_start[r] <= w < wave_start[r+1])
-// and runs that request's forward instance on its own wave index.
+// and runs that request's forward instance on its own wave index (offset by
+// the first wave of the request's chunk in this batch).
 __global__ __launch_bounds__(256) void fwd_batch_kernel(const BatchArgs b) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63;
@@ -22,7 +23,7 @@ __global__ __launch_bounds__(256) void fwd_batch_kernel(const BatchArgs b) {
     else hi = mid - 1;
   }
   const BatchDesc& d = b.desc[lo];
-  const int64_t lw = wid - b.wave_start[lo];
+  const int64_t lw = wid - b.wave_start[lo] + d.wave_begin;
   if (lw >= d.args.waves) return;
   switch (d.variant) {
     case 0: fwd_wave<FCFS_F32, 1, 4, 8, false>(d.args, lw, wslot, lane, smem); break;

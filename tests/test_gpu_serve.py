@@ -148,3 +148,51 @@ def test_replay_one_launch_per_request_and_discard():
         assert 0 < p50 <= p99 and rps > 0
     assert fc.fcfs_server_config(srv.handle, 99, 1) == fc.E_INVAL
     srv.close()
+
+
+@pytest.mark.parametrize("chunk", [37, 1000, 0])
+def test_chunked_requests_equal_solo(chunk):
+    """Requests larger than the chunk size run as chunks over several batches
+    (on both streams, after their input was generated on either); every
+    result equals its solo run bit for bit, and one is checked against the
+    oracle."""
+    import torch
+    import paper_2203_10670_amd as fc
+    srv = fc.Server(0, 2 << 30, 16)
+    assert fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_CHUNK_WAVES, chunk) == 0
+    reqs = [(3, 2, "bicubic", "reflect", "f32", (1, 3, 300, 400), 11),
+            (2, 3, "bilinear", "zero", "bf16", (2, 3, 77, 131), 12),
+            (5, 4, "nearest", "replicate", "f32", (1, 3, 500, 520), 13),
+            (7, 8, "bicubic", "zero", "bf16", (1, 3, 260, 700), 14),
+            (3, 2, "bilinear", "replicate", "f32", (1, 1, 9, 11), 15)]
+    tickets = [srv.submit(p, q, m, pad, dt, shape, seed=seed) for (p, q, m, pad, dt, shape, seed) in reqs]
+    _say("chunk", chunk, "submitted", len(tickets))
+    for k, (t, (p, q, m, pad, dt, shape, seed)) in enumerate(zip(tickets, reqs)):
+        r = srv.wait(t)
+        assert r.status == 0, (k, r.status)
+        got = fc.device_view(r.y, (shape[0], shape[1], r.h_out, r.w_out), dt)
+        x = storage_round(splitmix64_uniform(seed, int(np.prod(shape))).reshape(shape), dt)
+        solo = _solo(fc, torch.from_numpy(x).cuda().to(torch_dtype(dt)), p, q, m, pad)
+        assert torch.equal(got, solo), (chunk, k)
+        if k == 0:
+            assert_parity(got.float().cpu().numpy(), x, p, q, m, pad, dt, what="chunked %d" % chunk)
+        srv.release(t)
+    srv.close()
+
+
+def test_chunked_failure_stays_with_its_request():
+    """A failed batch fails the chunked request it held a chunk of (when its
+    last launched chunk completes) and nothing else."""
+    import paper_2203_10670_amd as fc
+    srv = fc.Server(0, 1 << 30, 8)
+    assert fc.fcfs_server_config(srv.handle, fc.FCFS_SERVER_CHUNK_WAVES, 50) == 0
+    assert fc.fcfs_server_debug(srv.handle, 2, 1) == 0
+    a = srv.submit(3, 2, "bicubic", "reflect", "f32", (1, 3, 300, 400), seed=1)
+    ra = srv.wait(a)
+    assert ra.status == fc.E_DEVICE
+    b = srv.submit(3, 2, "bicubic", "reflect", "f32", (1, 3, 300, 400), seed=2)
+    rb = srv.wait(b)
+    assert rb.status == 0
+    for t in (a, b):
+        srv.release(t)
+    srv.close()
