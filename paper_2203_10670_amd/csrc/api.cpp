@@ -195,6 +195,30 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     a->mix_kchunks = (int)std::max<int64_t>(1, std::min<int64_t>(8, rows));
     if (need_dw)
       bytes += align256(sizeof(float) * (size_t)a->mix_kchunks * plan->ah.p * plan->aw.p * a->Cout * c * 16);
+    // input gradient on MFMA: channel-last dy, packed weights and z over the
+    // extended positions (the offsets follow the partial sums)
+    const AxisTable &th = plan->ah, &tw = plan->aw;
+    a->mix_opad = (int)((c_out + 31) / 32 * 32);
+    a->mix_cpad = (int)((c + 63) / 64 * 64);
+    a->mix_eh0 = th.omin;
+    a->mix_eh = th.q * (a->Mh - 1) + th.omax - th.omin + 1;
+    a->mix_ew0 = tw.omin;
+    a->mix_ew1 = tw.q * (a->Mw - 1) + tw.omax;
+    a->mix_v0 = (int)floor_div(a->mix_ew0, tw.q);
+    a->mix_vw = (int)floor_div(a->mix_ew1, tw.q) - a->mix_v0 + 1;
+    a->mix_vpitch = (a->mix_vw + 3) / 4 * 4;
+    a->mix_vchunks = (a->mix_vw + 63) / 64;
+    const int64_t gemm_waves = n * (int64_t)a->mix_eh * tw.q * a->mix_vchunks * (a->mix_cpad / 64);
+    const int64_t fold_blocks = n * c * (int64_t)h * a->col_blocks;
+    a->mix_dx_gemm = gemm_waves / 4 < (1LL << 31) && fold_blocks < (1LL << 31);
+    if (a->mix_dx_gemm) {
+      a->mix_ws_dyc = bytes;
+      bytes += align256(sizeof(uint16_t) * (size_t)n * ho * wo * a->mix_opad);
+      a->mix_ws_wpk = bytes;
+      bytes += align256(sizeof(uint16_t) * (size_t)th.p * tw.p * 16 * a->mix_cpad * a->mix_opad);
+      a->mix_ws_z = bytes;
+      bytes += align256(sizeof(float) * (size_t)n * c * a->mix_eh * tw.q * a->mix_vpitch);
+    }
     *ws_bytes = bytes;
     return FCFS_OK;
   }
@@ -699,6 +723,11 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
   if (mix) {
     a.weight = nullptr;
     a.mix_weight = weight;
+    if (dx && a.mix_dx_gemm) {
+      a.mix_dyc = reinterpret_cast<uint16_t*>(ws + a.mix_ws_dyc);
+      a.mix_wpk = reinterpret_cast<uint16_t*>(ws + a.mix_ws_wpk);
+      a.mix_z = reinterpret_cast<float*>(ws + a.mix_ws_z);
+    }
     return dtype == FCFS_BF16 ? launch_backward_mix_bf16(a, stream) : launch_backward_mix_f16(a, stream);
   }
   switch (dtype) {

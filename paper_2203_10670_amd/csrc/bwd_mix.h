@@ -155,6 +155,217 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
     if (c0 + c < a.C) S::store(dxp + (int64_t)(c0 + c) * a.H * a.W, acc[c]);
 }
 
+// ---------------------------------------------------------------------------
+// Input gradient on MFMA. The adjoint of pad -> strided convolution ->
+// pixelshuffle is fold(C^T dy): z = C^T dy is the gradient with respect to the
+// padded (extended) input, and the pad adjoint folds z's margins back onto the
+// samples they copy (replicate: onto the edge sample; reflect: onto the mirror;
+// zero: dropped). z needs no folding logic, so it is a plain implicit GEMM per
+// residue class of the extended position e = (q_h u + rh, q_w v + rw):
+//   z[n][c][e] = sum over (jh, a) with off_h(jh) + a = rh (mod q_h), over
+//   (jw, b) likewise, and over o, of W[jh][jw][o][c][a][b] *
+//   dy[n][o][p_h (u - dh) + jh][p_w (v - dw) + jw],  d = (off + tap - r) / q,
+// with rows M = extended positions (16 consecutive v of one row and class),
+// columns N = input channels and reduction K = (tap pair, o). Two cheap
+// passes first lay dy out channel-last (dyc[n][ho][wo][o], o padded to a
+// multiple of 32) and the weights as wpk[jh][jw][a][b][c][o] (c padded to a
+// multiple of 64), so that every A and B fragment is one aligned 16-byte
+// global load (no LDS: each wave streams its own operands, and the caches
+// serve the re-reads). z is FP32, [n][c][extended row][rw][v]; the fold pass
+// then writes each dx sample once, rounded once to the storage type.
+constexpr int kDxgO = 32;    // outputs per MFMA K-step
+constexpr int kDxgC = 64;    // channels per wave (4 N tiles)
+constexpr int kDxgV = 64;    // positions per wave (4 M tiles of 16 consecutive v)
+
+// dyc[n][ho][wo][o] (o < opad, zero past C_out) from dy[n][o][ho][wo]: a block
+// takes 64 output columns of one output row, 64 outputs at a time through LDS.
+constexpr int kDxcPitch = 66;   // LDS tile pitch (16-bit units)
+__global__ __launch_bounds__(kThreads) void dx_mix_channel_last_kernel(const BwdArgs a) {
+  extern __shared__ float smem[];
+  uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);   // [64 outputs][kDxcPitch]
+  const int wblocks = (a.Wo + 63) / 64;
+  int64_t blk = blockIdx.x;
+  const int wb = (int)(blk % wblocks); blk /= wblocks;
+  const int ho = (int)(blk % a.Ho);
+  const int n = (int)(blk / a.Ho);
+  const uint16_t* dyb = reinterpret_cast<const uint16_t*>(a.dy);
+  uint16_t* out = a.mix_dyc;
+  const int64_t oplane = (int64_t)a.Ho * a.Wo;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int o0 = 0; o0 < a.mix_opad; o0 += 64) {
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {   // read: consecutive columns
+      const int o = o0 + r, wo = wb * 64 + tx;
+      tile[r * kDxcPitch + tx] =
+          (o < a.Cout && wo < a.Wo) ? dyb[((int64_t)n * a.Cout + o) * oplane + (int64_t)ho * a.Wo + wo] : 0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {   // write: consecutive outputs
+      const int wo = wb * 64 + r, o = o0 + tx;
+      if (wo < a.Wo && o < a.mix_opad) out[(((int64_t)n * a.Ho + ho) * a.Wo + wo) * a.mix_opad + o] = tile[tx * kDxcPitch + r];
+    }
+  }
+}
+
+// wpk[jh][jw][a][b][c][o] (c < cpad, o < opad, zeros past C_in and C_out)
+__global__ __launch_bounds__(kThreads) void dx_mix_pack_weights_kernel(const BwdArgs a) {
+  const int64_t total = (int64_t)a.th.p * a.tw_tab.p * 16 * a.mix_cpad * a.mix_opad;
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= total) return;
+  const int o = (int)(e % a.mix_opad);
+  int64_t r = e / a.mix_opad;
+  const int c = (int)(r % a.mix_cpad); r /= a.mix_cpad;
+  const int tap = (int)(r % 16);
+  const int ph = (int)(r / 16);   // jh * p_w + jw
+  const uint16_t* wt = reinterpret_cast<const uint16_t*>(a.mix_weight);
+  a.mix_wpk[e] = (o < a.Cout && c < a.C) ? wt[(((int64_t)ph * a.Cout + o) * a.C + c) * 16 + tap] : (uint16_t)0;
+}
+
+// z for 64 consecutive v of one extended row and width class, 64 channels.
+template <int DT>
+__global__ __launch_bounds__(kThreads) void dx_mix_gemm_kernel(const BwdArgs a) {
+  using M = Mfma<DT>;
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, g4 = lane >> 4;
+  int64_t wid = bwd::xcd_block() * 4 + (threadIdx.x >> 6);
+  const int ctiles = a.mix_cpad / kDxgC;
+  const int ct = (int)(wid % ctiles); wid /= ctiles;
+  const int vc = (int)(wid % a.mix_vchunks); wid /= a.mix_vchunks;
+  const int rw = (int)(wid % TW.q); wid /= TW.q;
+  const int er = (int)(wid % a.mix_eh); wid /= a.mix_eh;
+  const int n = (int)wid;
+  if (n >= a.planes_n) return;
+  const int eh = a.mix_eh0 + er;                       // extended row
+  const int rh = fwd::mod_pos(eh, TH.q), uh = (eh - rh) / TH.q;
+  const int c0 = ct * kDxgC;
+  const int v0 = a.mix_v0 + vc * kDxgV;                // first v of the wave
+  const uint16_t* const dyc = a.mix_dyc;
+  const uint16_t* const wpk = a.mix_wpk;
+  const int64_t rowstride = (int64_t)a.Wo * a.mix_opad;   // dyc row (16-bit units)
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // positions of this lane's A rows (extended column q_w v + rw, v = v0 + 16 mt + li)
+  int vv[4];
+  bool vin[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    vv[mt] = v0 + 16 * mt + li;
+    const int ew = TW.q * vv[mt] + rw;
+    vin[mt] = ew >= a.mix_ew0 && ew <= a.mix_ew1;
+  }
+  const int nsteps = a.mix_opad / kDxgO;
+  for (int jh = 0; jh < TH.p; ++jh)
+    for (int ta = 0; ta < 4; ++ta) {
+      const int dh4 = TH.off[jh] + ta - rh;
+      if (fwd::mod_pos(dh4, TH.q) != 0) continue;
+      const int mh = uh - dh4 / TH.q;                    // exact division
+      if (mh < 0 || mh >= a.Mh) continue;
+      const uint16_t* const dyrow = dyc + ((int64_t)n * a.Ho + TH.p * mh + jh) * rowstride;
+      for (int jw = 0; jw < TW.p; ++jw)
+        for (int tb = 0; tb < 4; ++tb) {
+          const int dw4 = TW.off[jw] + tb - rw;
+          if (fwd::mod_pos(dw4, TW.q) != 0) continue;
+          const int dq = dw4 / TW.q;
+          // A rows: dy column p_w (v - dq) + jw, valid for 0 <= v - dq < Mw
+          int64_t aoff[4];
+          bool aok[4];
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) {
+            const int mw = vv[mt] - dq;
+            aok[mt] = vin[mt] && mw >= 0 && mw < a.Mw;
+            aoff[mt] = aok[mt] ? (int64_t)(TW.p * mw + jw) * a.mix_opad + 8 * g4 : 0;
+          }
+          const uint16_t* const wrow =
+              wpk + ((((int64_t)jh * TW.p + jw) * 16 + ta * 4 + tb) * a.mix_cpad + c0 + li) * a.mix_opad + 8 * g4;
+          for (int os = 0; os < nsteps; ++os) {
+            u16x8 af[4], bf[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+              const u16x8 v = *reinterpret_cast<const u16x8*>(dyrow + aoff[mt] + kDxgO * os);
+              af[mt] = aok[mt] ? v : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+              bf[nt] = *reinterpret_cast<const u16x8*>(wrow + (int64_t)16 * nt * a.mix_opad + kDxgO * os);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+              for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+          }
+        }
+    }
+  // z[n][c][er][rw][v - v0_all] (rows of mix_vpitch, a multiple of 4, so the
+  // 4 positions of a lane are one aligned 16-byte store): lane (c = c0 +
+  // 16 nt + li) holds v = v0 + 16 mt + 4 g4 + i
+  const int64_t zrow = (int64_t)TW.q * a.mix_vpitch;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int c = c0 + 16 * nt + li;
+    if (c >= a.C) continue;
+    float* const zp = a.mix_z + (((int64_t)n * a.C + c) * a.mix_eh + er) * zrow + (int64_t)rw * a.mix_vpitch;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int vr = v0 + 16 * mt + 4 * g4 - a.mix_v0;
+      if (vr < a.mix_vpitch) *reinterpret_cast<f32x4*>(zp + vr) = acc[mt][nt];
+    }
+  }
+}
+
+// dx[n][c][i][j] = sum of z over the extended positions the padding maps to
+// (i, j) (itself, and for replicate / reflect the margin positions copying
+// it), in a fixed order, rounded once to the storage type.
+template <int DT>
+__global__ __launch_bounds__(kThreads) void dx_mix_fold_kernel(const BwdArgs a) {
+  using S = Store<DT>;
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+  int64_t blk = blockIdx.x;
+  const int cb = (int)(blk % a.col_blocks); blk /= a.col_blocks;
+  const int i = (int)(blk % a.H);
+  const int64_t pc = blk / a.H;   // n * C + c
+  const int j = cb * kThreads + threadIdx.x;
+  if (j >= a.W) return;
+  const int64_t zrow = (int64_t)TW.q * a.mix_vpitch;
+  const float* const zp = a.mix_z + pc * a.mix_eh * zrow;
+  auto zat = [&](int eh, int ew) -> float {
+    const int rw = fwd::mod_pos(ew, TW.q), v = (ew - rw) / TW.q;
+    return zp[(int64_t)(eh - a.mix_eh0) * zrow + (int64_t)rw * a.mix_vpitch + (v - a.mix_v0)];
+  };
+  // The extended positions that map to (i, j), in ascending order. Only
+  // samples within the margins' reach of an edge (or every sample of a short
+  // axis, which a reflection may wrap around) can receive folded terms.
+  const int lm_w = -a.mix_ew0, rm_w = a.mix_ew1 - (a.W - 1);   // margins beyond the edges
+  const int lm_h = -a.mix_eh0, rm_h = a.mix_eh0 + a.mix_eh - a.H;
+  const bool zone_w = a.pad != FCFS_PAD_ZERO && (j <= lm_w || j >= a.W - 1 - rm_w || a.W <= lm_w + rm_w + 2);
+  const bool zone_h = a.pad != FCFS_PAD_ZERO && (i <= lm_h || i >= a.H - 1 - rm_h || a.H <= lm_h + rm_h + 2);
+  float s = 0.f;
+  auto add_row = [&](int eh) {
+    if (zone_w)
+      for (int ew = a.mix_ew0; ew < 0; ++ew)
+        if (pad_source(ew, a.W, a.pad) == j) s += zat(eh, ew);
+    s += zat(eh, j);
+    if (zone_w)
+      for (int ew = a.W; ew <= a.mix_ew1; ++ew)
+        if (pad_source(ew, a.W, a.pad) == j) s += zat(eh, ew);
+  };
+  if (zone_h)
+    for (int eh = a.mix_eh0; eh < 0; ++eh)
+      if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
+  add_row(i);
+  if (zone_h)
+    for (int eh = a.H; eh < a.mix_eh0 + a.mix_eh; ++eh)
+      if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
+  (void)TH;
+  S::store(reinterpret_cast<typename S::T*>(a.dx) + pc * a.H * a.W + (int64_t)i * a.W + j, s);
+}
+
 constexpr int kDwOuts = 32;   // outputs per weight-gradient workgroup (2 M tiles)
 constexpr int kDwChan = 8;    // input channels per workgroup: 8 x 16 taps = 128 columns (8 N tiles)
 constexpr int kDwCells = 32;  // cells per MFMA reduction step
@@ -365,7 +576,20 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
   hipLaunchKernelGGL((bwd::adjoint_tables_kernel<DT>), dim3((unsigned)(((int64_t)a.H + a.W + kThreads - 1) / kThreads)),
                      block, 0, stream, a);
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
-  if (a.dx) {
+  if (a.dx && a.mix_z) {
+    // channel-last dy, packed weights, z on MFMA, then the fold
+    const int64_t cl_blocks = (int64_t)a.planes_n * a.Ho * ((a.Wo + 63) / 64);
+    hipLaunchKernelGGL(dx_mix_channel_last_kernel, dim3((unsigned)cl_blocks), block,
+                       sizeof(uint16_t) * 64 * kDxcPitch, stream, a);
+    const int64_t wtotal = (int64_t)a.th.p * a.tw_tab.p * 16 * a.mix_cpad * a.mix_opad;
+    hipLaunchKernelGGL(dx_mix_pack_weights_kernel, dim3((unsigned)((wtotal + kThreads - 1) / kThreads)), block, 0,
+                       stream, a);
+    const int64_t waves = (int64_t)a.planes_n * a.mix_eh * a.tw_tab.q * a.mix_vchunks * (a.mix_cpad / kDxgC);
+    hipLaunchKernelGGL((dx_mix_gemm_kernel<DT>), dim3((unsigned)((waves + 3) / 4)), block, 0, stream, a);
+    const int64_t fblocks = (int64_t)a.planes_n * a.C * a.H * a.col_blocks;
+    hipLaunchKernelGGL((dx_mix_fold_kernel<DT>), dim3((unsigned)fblocks), block, 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  } else if (a.dx) {
     const int64_t blocks = (int64_t)a.planes_n * a.H * a.col_blocks * a.mix_cblocks;
     const size_t lds = sizeof(uint32_t) * a.tw_tab.p * 4 * kDxBlock;
     hipLaunchKernelGGL((dx_mix_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);

@@ -102,6 +102,16 @@ struct BwdArgs {
   const void* mix_weight;  // [p_h][p_w][Cout][C][4][4], 16-bit storage
   int mix_cblocks;         // input-gradient workgroups per row block: ceil(C / 32)
   int mix_otiles, mix_ctiles, mix_kchunks;   // weight gradient: 32 outputs x 8 channels x chunks of cell rows
+  // input gradient on MFMA (workspace): channel-last dy, packed weights, and
+  // z = C^T dy over the extended positions [eh0, eh0 + eh) x [ew0, ew1],
+  // stored [n][c][row][width class][v - v0] (v0 .. v0 + vw - 1)
+  uint16_t* mix_dyc;       // [n][ho][wo][opad]
+  uint16_t* mix_wpk;       // [p_h][p_w][4][4][cpad][opad]
+  float* mix_z;            // null: the input gradient runs on the vector ALUs
+  int mix_opad, mix_cpad;  // C_out rounded up to 32, C_in rounded up to 64
+  int mix_eh0, mix_eh, mix_ew0, mix_ew1, mix_v0, mix_vw, mix_vpitch, mix_vchunks;   // vpitch: vw rounded up to 4
+  int mix_dx_gemm;         // the grids fit: the input gradient on MFMA
+  size_t mix_ws_dyc, mix_ws_wpk, mix_ws_z;   // workspace offsets of the three buffers
   AxisTable th, tw_tab;
 };
 

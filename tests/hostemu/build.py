@@ -23,7 +23,7 @@ def build(sanitize: bool = True) -> str:
                  [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")])
     if os.path.exists(OUT) and os.path.getmtime(OUT) >= newest:
         return OUT
-    flags = ["-std=c++20", "-O1", "-g", "-fPIC", "-shared", "-pthread", "-w",
+    flags = ["-std=c++20", "-O2", "-g", "-fPIC", "-shared", "-pthread", "-w",
              "-I", HERE, "-I", os.path.join(ROOT, "include"), "-I", CSRC] + EXTRA
     if sanitize:
         flags += ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]

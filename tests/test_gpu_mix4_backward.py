@@ -83,3 +83,33 @@ def test_mix4_backward_deterministic_and_autograd():
     torch.cuda.synchronize()
     assert torch.equal(xr.grad, a[0])
     assert torch.equal(wr.grad, a[1].to(torch.bfloat16))
+
+
+def test_mix4_input_gradient_16x64x512_sampled():
+    """The 16x64x512^2 layer at 5/4 (BF16, 64 -> 64): the input gradient at the
+    benchmarked size, checked on corner and interior windows against the
+    oracle's adjoint of a crop that holds every output reading them."""
+    import torch
+    import paper_2203_10670_amd as fc
+    N, C, H, W, p, q = 16, 64, 512, 512, 5, 4
+    Ho = Wo = 640
+    dy = storage_round(synth.normal(8, (N, C, Ho, Wo)), "bf16")
+    w = storage_round(synth.normal(5, (p, p, C, C, 4, 4), std=1 / 32), "bf16")
+    pl = fc.Plan(p, q, "mix4", "reflect")
+    dx, _ = pl.backward(torch.from_numpy(dy).cuda().to(torch.bfloat16), (N, C, H, W),
+                        weight=torch.from_numpy(w).cuda().to(torch.bfloat16).contiguous(), need_dx=True)
+    torch.cuda.synchronize()
+    _say("mix4 dx 16x64x512 done")
+    # crop of input rows/cols [R0, R1) at multiples of q; outputs p*R0/q .. p*R1/q;
+    # dx is compared 8 samples inside the crop's cut edges
+    for n, (R0, R1), (C0, C1) in [(0, (0, 32), (0, 32)), (15, (480, 512), (480, 512)), (7, (240, 272), (100, 132))]:
+        dyc = dy[n:n + 1, :, p * R0 // q: p * R1 // q, p * C0 // q: p * C1 // q]
+        shape = (1, C, R1 - R0, C1 - C0)
+        r, _ = oracle.backward(dyc.astype(np.float64), shape, p, q, "mix4", "reflect", weight=w)
+        S, _ = oracle.condition_backward(dyc, shape, p, q, "mix4", "reflect", weight=w)
+        ra, rb = (0 if R0 == 0 else 8), (R1 - R0 if R1 == H else R1 - R0 - 8)
+        ca, cb = (0 if C0 == 0 else 8), (C1 - C0 if C1 == W else C1 - C0 - 8)
+        g = dx[n:n + 1, :, R0 + ra: R0 + rb, C0 + ca: C0 + cb].float().cpu().numpy()
+        rr, SS = r[:, :, ra:rb, ca:cb], S[:, :, ra:rb, ca:cb]
+        bad = np.abs(g - rr) > UNIT["bf16"] * np.abs(rr) + UNIT_ABS["bf16"] + 1e-5 * SS + 1e-30
+        assert not bad.any(), (n, R0, C0, int(bad.sum()))

@@ -29,12 +29,16 @@ def _run(cases):
     assert r.stdout.count(" ok") == len(cases), r.stdout[-4000:]
 
 
+# Every factor with every method when FCFS_HOSTEMU_ALL=1; by default every
+# factor with one method (rotating) and the benchmarked factors with all three.
+ALL = os.environ.get("FCFS_HOSTEMU_ALL") == "1"
 FIXED = []
-for (p, q) in [(3, 2), (2, 3), (5, 4), (4, 5), (3, 4), (1, 1), (4, 1), (1, 4), (6, 4), (2, 11), (27, 11),
-               (1, 32), (32, 31)]:
-    for m in ["nearest", "bilinear", "bicubic"]:
-        FIXED.append({"p": p, "q": q, "method": m, "pad": ["zero", "replicate", "reflect"][(p + q) % 3],
-                      "shape": [1, 2, 23, 70]})
+for i, (p, q) in enumerate([(3, 2), (2, 3), (5, 4), (4, 5), (3, 4), (1, 1), (4, 1), (1, 4), (6, 4), (2, 11),
+                            (27, 11), (1, 32), (32, 31)]):
+    for k, m in enumerate(["nearest", "bilinear", "bicubic"]):
+        if ALL or i < 4 or k == i % 3:
+            FIXED.append({"p": p, "q": q, "method": m, "pad": ["zero", "replicate", "reflect"][(p + q) % 3],
+                          "shape": [1, 2, 23, 70]})
 
 
 def test_fixed_methods_all_factors():
@@ -93,17 +97,19 @@ def test_channel_mixing_backward():
     # input gradient (gathered over the adjoint tables) and weight gradient
     # (MFMA over cells, chunks added in order), 16-bit storage
     cases = []
-    for (p, q, pad, dt, shape, cout) in [(5, 4, "reflect", "bf16", [2, 3, 9, 40], 5),
-                                          (3, 2, "zero", "f16", [1, 9, 7, 35], 33),
-                                          (2, 3, "replicate", "bf16", [1, 2, 11, 300], 3),
-                                          (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2),
-                                          # two column blocks, both columns of a thread live in the first
-                                          (5, 4, "reflect", "bf16", [1, 3, 5, 700], 6),
-                                          # 8 width phases and several output tiles; q = 7
-                                          (8, 3, "zero", "bf16", [1, 4, 10, 100], 70),
-                                          (4, 7, "reflect", "f16", [1, 9, 17, 270], 20)]:
-        cases.append({"mode": "bwd", "p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": shape,
-                      "cout": cout})
+    for i, (p, q, pad, dt, shape, cout) in enumerate([
+            (5, 4, "reflect", "bf16", [2, 3, 9, 40], 5),
+            (3, 2, "zero", "f16", [1, 9, 7, 35], 33),
+            # two column blocks, both columns of a thread live in the first
+            (5, 4, "reflect", "bf16", [1, 3, 5, 700], 6),
+            (2, 3, "replicate", "bf16", [1, 2, 11, 300], 3),
+            (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2),
+            # 8 width phases and several output tiles
+            (8, 3, "zero", "bf16", [1, 4, 10, 100], 70),
+            (4, 7, "reflect", "f16", [1, 9, 17, 270], 20)]):
+        if ALL or i < 3:
+            cases.append({"mode": "bwd", "p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": shape,
+                          "cout": cout})
     _run(cases)
 
 
@@ -173,7 +179,8 @@ def test_channel_mixing_fp32():
     _run([{"p": 5, "q": 4, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 2, 8, 8], "cout": 2},
           {"p": 5, "q": 4, "method": "mix4", "pad": "reflect", "dtype": "f32", "shape": [2, 6, 13, 70],
            "cout": 70},
-          {"p": 2, "q": 7, "method": "mix4", "pad": "reflect", "dtype": "f32", "shape": [1, 5, 30, 60], "cout": 3},
           {"p": 9, "q": 8, "method": "mix4", "pad": "replicate", "dtype": "f32", "shape": [1, 3, 20, 75],
-           "cout": 4},
-          {"p": 3, "q": 2, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 9, 7, 35], "cout": 17}])
+           "cout": 4}] +
+         ([{"p": 2, "q": 7, "method": "mix4", "pad": "reflect", "dtype": "f32", "shape": [1, 5, 30, 60], "cout": 3},
+           {"p": 3, "q": 2, "method": "mix4", "pad": "zero", "dtype": "f32", "shape": [1, 9, 7, 35], "cout": 17}]
+          if ALL else []))
