@@ -159,6 +159,32 @@ static int adjoint_cmax(const AxisTable& t, int n, int cells, int pad) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The channel-mixing weight gradient as a GEMM over re-laid-out operands
+// (otherwise the per-phase staging kernel).
+constexpr bool kMixDwGemm = false;
+
+// The (phase, tap) pairs of each residue class of an axis's extended index,
+// for the channel-mixing input gradient: e = q u + r is read by tap t of
+// phase j in cell u - d when off[j] + t = r + q d. Also the range of d.
+static void mix_residue_lists(const AxisTable& t, int* start, int* list, int* dmin, int* dmax) {
+  int k = 0;
+  *dmin = 1 << 20;
+  *dmax = -(1 << 20);
+  for (int r = 0; r < t.q; ++r) {
+    start[r] = k;
+    for (int j = 0; j < t.p; ++j)
+      for (int tap = 0; tap < 4; ++tap) {
+        const int s = t.off[j] + tap - r;
+        if (mod_pos(s, t.q) != 0) continue;
+        const int d = (int)floor_div(s, t.q);
+        list[k++] = j | tap << 5 | (d + 64) << 7;
+        *dmin = std::min(*dmin, d);
+        *dmax = std::max(*dmax, d);
+      }
+  }
+  start[t.q] = k;
+}
+
 // Fills the size-dependent fields of the backward arguments and returns the
 // workspace layout: [height table][width table][weight-gradient partials].
 static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, int64_t c_out, int h, int w,
@@ -193,31 +219,101 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     a->mix_ctiles = (int)((c + 7) / 8);
     const int64_t rows = n * (int64_t)a->Mh;
     a->mix_kchunks = (int)std::max<int64_t>(1, std::min<int64_t>(8, rows));
-    if (need_dw)
-      bytes += align256(sizeof(float) * (size_t)a->mix_kchunks * plan->ah.p * plan->aw.p * a->Cout * c * 16);
-    // input gradient on MFMA: channel-last dy, packed weights and z over the
-    // extended positions (the offsets follow the partial sums)
     const AxisTable &th = plan->ah, &tw = plan->aw;
     a->mix_opad = (int)((c_out + 31) / 32 * 32);
     a->mix_cpad = (int)((c + 63) / 64 * 64);
+    // weight gradient on MFMA: dy by phase and x by tap offset, cells in
+    // blocks of 32; chunks of cell rows for about 2048 workgroups
+    a->mix_dwopad = (int)((c_out + 63) / 64 * 64);
+    a->mix_ncb = (a->Mw + 31) / 32;
+    a->mix_s0 = tw.omin;
+    a->mix_ns = tw.omax - tw.omin + 1;
+    a->mix_dwcells = std::max(8, std::min(32, (256 / tw.p) / 8 * 8));
+    a->mix_dwxcells = tw.q <= 8 ? 32 : 8;
+    const int64_t per_chunk = (int64_t)th.p * tw.p * 4 * (a->mix_dwopad / 64) * (a->mix_cpad / 64);
+    a->mix_wchunks = (int)std::max<int64_t>(1, std::min<int64_t>(rows, (2048 + per_chunk - 1) / per_chunk));
+    const int64_t erows = (int64_t)th.q * (a->Mh - 1) + th.omax - th.omin + 1;
+    const int64_t dyw_elems = n * (int64_t)ho * tw.p * a->mix_ncb * 32 * a->mix_dwopad;
+    const int64_t xa_elems = n * erows * a->mix_ns * a->mix_ncb * 32 * a->mix_cpad;
+    const int64_t ncb32 = (int64_t)a->mix_ncb * 32;
+    a->mix_dw_gemm = kMixDwGemm && need_dw && per_chunk * a->mix_wchunks < (1LL << 31) &&
+                     n * ho * ((ncb32 + a->mix_dwcells - 1) / a->mix_dwcells) * (a->mix_dwopad / 64) < (1LL << 31) &&
+                     n * erows * ((ncb32 + a->mix_dwxcells - 1) / a->mix_dwxcells) * (a->mix_cpad / 64) < (1LL << 31) &&
+                     (int64_t)th.p * tw.p * 16 * c_out * c < (1LL << 31);
+    if (need_dw)
+      bytes += align256(sizeof(float) * (size_t)(a->mix_dw_gemm ? a->mix_wchunks : a->mix_kchunks) * th.p * tw.p *
+                        a->Cout * c * 16);
+    // input gradient on MFMA: channel-last dy, packed weights and the edge
+    // buffer (the offsets follow the partial sums)
+    int dhmin, dhmax, dwmin, dwmax;
+    mix_residue_lists(th, a->mix_hl_start, a->mix_hl, &dhmin, &dhmax);
+    mix_residue_lists(tw, a->mix_wl_start, a->mix_wl, &dwmin, &dwmax);
+    // the extended positions the taps read, and the GEMM's range: those and
+    // every input sample (samples no tap reads get 0)
     a->mix_eh0 = th.omin;
-    a->mix_eh = th.q * (a->Mh - 1) + th.omax - th.omin + 1;
+    a->mix_eh1 = th.q * (a->Mh - 1) + th.omax;
     a->mix_ew0 = tw.omin;
     a->mix_ew1 = tw.q * (a->Mw - 1) + tw.omax;
-    a->mix_v0 = (int)floor_div(a->mix_ew0, tw.q);
-    a->mix_vw = (int)floor_div(a->mix_ew1, tw.q) - a->mix_v0 + 1;
-    a->mix_vpitch = (a->mix_vw + 3) / 4 * 4;
-    a->mix_vchunks = (a->mix_vw + 63) / 64;
-    const int64_t gemm_waves = n * (int64_t)a->mix_eh * tw.q * a->mix_vchunks * (a->mix_cpad / 64);
-    const int64_t fold_blocks = n * c * (int64_t)h * a->col_blocks;
-    a->mix_dx_gemm = gemm_waves / 4 < (1LL << 31) && fold_blocks < (1LL << 31);
+    a->mix_r0 = std::min(a->mix_eh0, 0);
+    a->mix_rows = std::max(a->mix_eh1 + 1, h) - a->mix_r0;
+    a->mix_v0 = (int)std::min<int64_t>(floor_div(a->mix_ew0, tw.q), 0);
+    const int64_t v1 = std::max<int64_t>(floor_div(a->mix_ew1, tw.q) + 1, (w + tw.q - 1) / tw.q);
+    a->mix_vw = (int)(v1 - a->mix_v0);
+    // a workgroup takes every width class of kw chunks of 16 mtn positions
+    // (one chunk per wave when q_w <= 4)
+    const int chunks = (a->mix_vw + 63) / 64;
+    a->mix_mtn = (a->mix_vw + 16 * chunks - 1) / (16 * chunks);
+    a->mix_kw = tw.q >= 4 ? 1 : 4 / tw.q;
+    a->mix_vgroups = (chunks + a->mix_kw - 1) / a->mix_kw;
+    a->mix_vchunks = a->mix_vgroups * a->mix_kw;
+    a->mix_lds_epi = tw.q * a->mix_kw <= 8;
+    // dy cells the A rows reach: v - d for v in the chunks and every d
+    const int64_t vend = a->mix_v0 + (int64_t)a->mix_vchunks * 16 * a->mix_mtn;
+    a->mix_dleft = std::max(0, dwmax - a->mix_v0);
+    const int64_t dright = std::max<int64_t>(0, vend - 1 - dwmin - (a->Mw - 1));
+    const int64_t dcells = a->mix_dleft + a->Mw + dright;
+    a->mix_dcells = (int)std::min<int64_t>(dcells, 1 << 30);
+    a->mix_clcells = std::max(1, 128 / tw.p);
+    // fold zones of replicate / reflect: the samples the margins copy (every
+    // sample of an axis short enough for a reflection to wrap)
+    auto zone = [&](int len, int e0, int e1, int* lo, int* hi) {
+      const int lm = std::max(0, -e0), rm = std::max(0, e1 - (len - 1));
+      if (plan->pad == FCFS_PAD_ZERO) {
+        *lo = *hi = 0;
+      } else if (len <= lm + rm + 2) {
+        *lo = len;
+        *hi = 0;
+      } else {
+        *lo = lm + 1;
+        *hi = rm + 1;
+      }
+    };
+    zone(h, a->mix_eh0, a->mix_eh1, &a->mix_top, &a->mix_bot);
+    zone(w, a->mix_ew0, a->mix_ew1, &a->mix_cl, &a->mix_cr);
+    const int64_t ec0 = (int64_t)tw.q * a->mix_v0, ecols = (int64_t)tw.q * a->mix_vw;
+    a->mix_rr = (int)((a->mix_top - a->mix_r0) + (a->mix_r0 + a->mix_rows - (h - a->mix_bot)));
+    a->mix_cc = (int)((a->mix_cl - ec0) + (ec0 + ecols - (w - a->mix_cr)));
+    a->mix_edge_c = (int64_t)a->mix_rr * ecols;
+    a->mix_edge_per = (int64_t)(a->mix_top + a->mix_bot) * w + (int64_t)(h - a->mix_top - a->mix_bot) * (a->mix_cl + a->mix_cr);
+    const int64_t gemm_blocks = n * (int64_t)a->mix_rows * a->mix_vgroups * (a->mix_cpad / 64);
+    const int64_t edge_blocks = (n * c * a->mix_edge_per + 255) / 256;
+    const int64_t dyc_row = dcells * tw.p * a->mix_opad;
+    a->mix_dx_gemm = gemm_blocks < (1LL << 31) && edge_blocks < (1LL << 31) && dyc_row < (1LL << 30) &&
+                     (int64_t)th.p * tw.p * 16 * a->mix_cpad * a->mix_opad < (1LL << 31);
     if (a->mix_dx_gemm) {
       a->mix_ws_dyc = bytes;
-      bytes += align256(sizeof(uint16_t) * (size_t)n * ho * wo * a->mix_opad);
+      bytes += align256(sizeof(uint16_t) * (size_t)n * ho * dyc_row);
       a->mix_ws_wpk = bytes;
       bytes += align256(sizeof(uint16_t) * (size_t)th.p * tw.p * 16 * a->mix_cpad * a->mix_opad);
-      a->mix_ws_z = bytes;
-      bytes += align256(sizeof(float) * (size_t)n * c * a->mix_eh * tw.q * a->mix_vpitch);
+      a->mix_ws_edge = bytes;
+      if (plan->pad != FCFS_PAD_ZERO)
+        bytes += align256(sizeof(float) * (size_t)n * c * (a->mix_edge_c + (int64_t)a->mix_rows * a->mix_cc));
+    }
+    if (a->mix_dw_gemm) {
+      a->mix_ws_dyw = bytes;
+      bytes += align256(sizeof(uint16_t) * (size_t)dyw_elems);
+      a->mix_ws_xa = bytes;
+      bytes += align256(sizeof(uint16_t) * (size_t)xa_elems);
     }
     *ws_bytes = bytes;
     return FCFS_OK;
@@ -726,7 +822,11 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
     if (dx && a.mix_dx_gemm) {
       a.mix_dyc = reinterpret_cast<uint16_t*>(ws + a.mix_ws_dyc);
       a.mix_wpk = reinterpret_cast<uint16_t*>(ws + a.mix_ws_wpk);
-      a.mix_z = reinterpret_cast<float*>(ws + a.mix_ws_z);
+      a.mix_edge = plan->pad != FCFS_PAD_ZERO ? reinterpret_cast<float*>(ws + a.mix_ws_edge) : nullptr;
+    }
+    if (dw && a.mix_dw_gemm) {
+      a.mix_dyw = reinterpret_cast<uint16_t*>(ws + a.mix_ws_dyw);
+      a.mix_xa = reinterpret_cast<uint16_t*>(ws + a.mix_ws_xa);
     }
     return dtype == FCFS_BF16 ? launch_backward_mix_bf16(a, stream) : launch_backward_mix_f16(a, stream);
   }

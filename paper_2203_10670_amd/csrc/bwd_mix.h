@@ -160,210 +160,321 @@ __global__ __launch_bounds__(kThreads) void dx_mix_kernel(const BwdArgs a) {
 // pixelshuffle is fold(C^T dy): z = C^T dy is the gradient with respect to the
 // padded (extended) input, and the pad adjoint folds z's margins back onto the
 // samples they copy (replicate: onto the edge sample; reflect: onto the mirror;
-// zero: dropped). z needs no folding logic, so it is a plain implicit GEMM per
-// residue class of the extended position e = (q_h u + rh, q_w v + rw):
-//   z[n][c][e] = sum over (jh, a) with off_h(jh) + a = rh (mod q_h), over
-//   (jw, b) likewise, and over o, of W[jh][jw][o][c][a][b] *
-//   dy[n][o][p_h (u - dh) + jh][p_w (v - dw) + jw],  d = (off + tap - r) / q,
-// with rows M = extended positions (16 consecutive v of one row and class),
-// columns N = input channels and reduction K = (tap pair, o). Two cheap
-// passes first lay dy out channel-last (dyc[n][ho][wo][o], o padded to a
-// multiple of 32) and the weights as wpk[jh][jw][a][b][c][o] (c padded to a
-// multiple of 64), so that every A and B fragment is one aligned 16-byte
-// global load (no LDS: each wave streams its own operands, and the caches
-// serve the re-reads). z is FP32, [n][c][extended row][rw][v]; the fold pass
-// then writes each dx sample once, rounded once to the storage type.
+// zero: dropped). z itself is a plain implicit GEMM per residue class of the
+// extended position e = (q_h u + rh, q_w v + rw):
+//   z[n][c][e] = sum over (jh, a) with off_h(jh) + a = rh + q_h dh, over
+//   (jw, b) with off_w(jw) + b = rw + q_w dw, and over o, of
+//   W[jh][jw][o][c][a][b] * dy[n][o][p_h (u - dh) + jh][p_w (v - dw) + jw],
+// with rows M = extended positions (consecutive v of one row and class),
+// columns N = input channels and reduction K = (tap pair, o).
+//
+// Two cheap passes first lay out dy by width phase and 32 outputs, cells
+// contiguous with zero margin cells on both sides (dyc[n][ho][jw][o / 32]
+// [cell][o % 32]), and the weights as wpk[jh][jw][a][b][o / 32][o % 32 / 8]
+// [c][o % 8]. An A fragment (16 cells x 32 outputs) and a B fragment (32
+// outputs x 16 channels) are then each 1 KB of consecutive memory, one
+// 16-byte load per lane, and a cell outside the row reads zeros.
+//
+// A workgroup takes one extended row, kw chunks of 16 mtn consecutive v and
+// 64 channels, for every width class (waves take the (class, chunk) slots in
+// turn; with q_w = 4 one class each, so the four waves read the same dy
+// cells and share them in L1). A wave walks its class's (tap pair, 32
+// outputs) steps with the next step's fragments in flight during the current
+// step's MFMAs. The epilogue interleaves the classes in LDS and writes each dx
+// row segment contiguously, rounded once; the samples the pad adjoint folds
+// (and the margins) go to the edge buffer in FP32, and a last pass adds each
+// sample's preimages there in ascending order and rounds once.
 constexpr int kDxgO = 32;    // outputs per MFMA K-step
-constexpr int kDxgC = 64;    // channels per wave (4 N tiles)
-constexpr int kDxgV = 64;    // positions per wave (4 M tiles of 16 consecutive v)
+constexpr int kDxgC = 64;    // channels per workgroup (4 N tiles)
 
-// dyc[n][ho][wo][o] (o < opad, zero past C_out) from dy[n][o][ho][wo]: a block
-// takes 64 output columns of one output row, 64 outputs at a time through LDS.
-constexpr int kDxcPitch = 66;   // LDS tile pitch (16-bit units)
+// dyc from dy[n][o][ho][wo]: a block takes kw cells (all p_w phases, at most
+// 128 columns col = cell * p_w + jw, wo = col - dleft * p_w; zeros outside
+// the row) of one output row, 64 outputs at a time through an LDS tile
+// [column][output]. With W_out even a lane reads an aligned column pair of 8
+// outputs (8 dword loads, coalesced over pairs) and writes two 16-byte
+// column chunks; then each lane moves 16-byte chunks of 8 outputs, ordered
+// so that consecutive lanes write consecutive bytes of dyc.
+constexpr int kDxcPitch = 72;   // LDS tile pitch (16-bit units): [128 columns][64 outputs + 8]
 __global__ __launch_bounds__(kThreads) void dx_mix_channel_last_kernel(const BwdArgs a) {
   extern __shared__ float smem[];
-  uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);   // [64 outputs][kDxcPitch]
-  const int wblocks = (a.Wo + 63) / 64;
+  uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
+  const int pw = a.tw_tab.p;
+  const int kcl = a.mix_clcells;   // cells per block
+  const int cblocks = (a.mix_dcells + kcl - 1) / kcl;
   int64_t blk = blockIdx.x;
-  const int wb = (int)(blk % wblocks); blk /= wblocks;
+  const int cb = (int)(blk % cblocks); blk /= cblocks;
   const int ho = (int)(blk % a.Ho);
   const int n = (int)(blk / a.Ho);
-  const uint16_t* dyb = reinterpret_cast<const uint16_t*>(a.dy);
-  uint16_t* out = a.mix_dyc;
+  const int k0 = cb * kcl;
+  const int ncols = kcl * pw;
+  const int wlo = k0 * pw - a.mix_dleft * pw;   // dy column of tile column 0
+  const uint16_t* const dyb = reinterpret_cast<const uint16_t*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo + (int64_t)ho * a.Wo;
   const int64_t oplane = (int64_t)a.Ho * a.Wo;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int nst = a.mix_opad / kDxgO;
+  uint16_t* const orow = a.mix_dyc + ((int64_t)n * a.Ho + ho) * pw * nst * a.mix_dcells * kDxgO;
+  const bool pairs = (a.Wo & 1) == 0 && (reinterpret_cast<uintptr_t>(a.dy) & 3) == 0;
   for (int o0 = 0; o0 < a.mix_opad; o0 += 64) {
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {   // read: consecutive columns
-      const int o = o0 + r, wo = wb * 64 + tx;
-      tile[r * kDxcPitch + tx] =
-          (o < a.Cout && wo < a.Wo) ? dyb[((int64_t)n * a.Cout + o) * oplane + (int64_t)ho * a.Wo + wo] : 0;
+    if (pairs) {
+      // items (pair m, 8 outputs g): pairs cover [wlo, wlo + ncols)
+      const int m0 = wlo >> 1;   // floor
+      const int npairs = ((wlo + ncols - 1) >> 1) - m0 + 1;
+      for (int it = threadIdx.x; it < npairs * 8; it += kThreads) {
+        const int m = it % npairs, g = it / npairs;
+        const int w0 = 2 * (m0 + m);
+        const bool in = w0 >= 0 && w0 < a.Wo;   // W_out even: both columns or neither
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int o = o0 + 8 * g + i;
+          v[i] = (in && o < a.Cout) ? *reinterpret_cast<const uint32_t*>(dyb + (int64_t)o * oplane + w0) : 0u;
+        }
+        u16x8 lo, hi;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          lo[i] = (uint16_t)(v[i] & 0xffffu);
+          hi[i] = (uint16_t)(v[i] >> 16);
+        }
+        const int c = w0 - wlo;
+        if (c >= 0 && c < ncols) *reinterpret_cast<u16x8*>(tile + c * kDxcPitch + 8 * g) = lo;
+        if (c + 1 >= 0 && c + 1 < ncols) *reinterpret_cast<u16x8*>(tile + (c + 1) * kDxcPitch + 8 * g) = hi;
+      }
+    } else {
+      for (int it = threadIdx.x; it < 64 * ncols; it += kThreads) {
+        const int c = it % ncols, r = it / ncols;
+        const int wo = wlo + c, o = o0 + r;
+        tile[c * kDxcPitch + r] = (wo >= 0 && wo < a.Wo && o < a.Cout) ? dyb[(int64_t)o * oplane + wo] : 0;
+      }
     }
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {   // write: consecutive outputs
-      const int wo = wb * 64 + r, o = o0 + tx;
-      if (wo < a.Wo && o < a.mix_opad) out[(((int64_t)n * a.Ho + ho) * a.Wo + wo) * a.mix_opad + o] = tile[tx * kDxcPitch + r];
+    // chunks (jw, 32 outputs s, cell, 8 outputs g), g fastest
+    const int nchunks = pw * 2 * kcl * 4;
+    for (int e = threadIdx.x; e < nchunks; e += kThreads) {
+      const int g = e & 3, cell = (e >> 2) % kcl, sj = (e >> 2) / kcl;
+      const int sl = sj & 1, jw = sj >> 1;
+      const int os = o0 / kDxgO + sl;
+      if (os >= nst || k0 + cell >= a.mix_dcells) continue;
+      *reinterpret_cast<u16x8*>(orow + (((int64_t)jw * nst + os) * a.mix_dcells + k0 + cell) * kDxgO + 8 * g) =
+          *reinterpret_cast<const u16x8*>(tile + (cell * pw + jw) * kDxcPitch + sl * kDxgO + 8 * g);
     }
   }
 }
 
-// wpk[jh][jw][a][b][c][o] (c < cpad, o < opad, zeros past C_in and C_out)
+// wpk from W[jh][jw][o][c][a][b] (zeros past C_in and C_out)
 __global__ __launch_bounds__(kThreads) void dx_mix_pack_weights_kernel(const BwdArgs a) {
   const int64_t total = (int64_t)a.th.p * a.tw_tab.p * 16 * a.mix_cpad * a.mix_opad;
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= total) return;
-  const int o = (int)(e % a.mix_opad);
-  int64_t r = e / a.mix_opad;
+  const int i = (int)(e % 8);
+  int64_t r = e / 8;
   const int c = (int)(r % a.mix_cpad); r /= a.mix_cpad;
+  const int og = (int)(r % (a.mix_opad / 8)); r /= a.mix_opad / 8;   // (o / 32, o % 32 / 8)
   const int tap = (int)(r % 16);
   const int ph = (int)(r / 16);   // jh * p_w + jw
+  const int o = 8 * og + i;
   const uint16_t* wt = reinterpret_cast<const uint16_t*>(a.mix_weight);
   a.mix_wpk[e] = (o < a.Cout && c < a.C) ? wt[(((int64_t)ph * a.Cout + o) * a.C + c) * 16 + tap] : (uint16_t)0;
 }
 
-// z for 64 consecutive v of one extended row and width class, 64 channels.
-template <int DT>
-__global__ __launch_bounds__(kThreads) void dx_mix_gemm_kernel(const BwdArgs a) {
+// Edge buffer index of extended position (eh, ew), which lies in a fold zone
+// row (part R: [zone row][ew - q_w v0]) or else a fold zone column (part C:
+// [eh - r0][zone column]).
+__device__ __forceinline__ int64_t edge_index(const BwdArgs& a, int64_t pc, int eh, int ew) {
+  const int ec0 = a.tw_tab.q * a.mix_v0, ecols = a.tw_tab.q * a.mix_vw;
+  if (eh < a.mix_top || eh >= a.H - a.mix_bot) {
+    const int r = eh < a.mix_top ? eh - a.mix_r0 : (a.mix_top - a.mix_r0) + eh - (a.H - a.mix_bot);
+    return (pc * a.mix_rr + r) * ecols + (ew - ec0);
+  }
+  const int cc = ew < a.mix_cl ? ew - ec0 : (a.mix_cl - ec0) + ew - (a.W - a.mix_cr);
+  return (int64_t)a.planes_n * a.C * a.mix_edge_c + (pc * a.mix_rows + (eh - a.mix_r0)) * a.mix_cc + cc;
+}
+
+// One extended row, kw chunks of 16 MTN consecutive v, 64 channels, every
+// width class.
+template <int DT, int MTN>
+__global__ __launch_bounds__(kThreads, 3) void dx_mix_gemm_kernel(const BwdArgs a) {
   using M = Mfma<DT>;
+  using S = Store<DT>;
+  using TS = typename S::T;
+  extern __shared__ float smem[];
+  uint16_t* const otile = reinterpret_cast<uint16_t*>(smem);   // [64 channels][cols] (storage type)
   const AxisTable& TH = a.th;
   const AxisTable& TW = a.tw_tab;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, g4 = lane >> 4;
-  int64_t wid = bwd::xcd_block() * 4 + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t blk = bwd::xcd_block();
   const int ctiles = a.mix_cpad / kDxgC;
-  const int ct = (int)(wid % ctiles); wid /= ctiles;
-  const int vc = (int)(wid % a.mix_vchunks); wid /= a.mix_vchunks;
-  const int rw = (int)(wid % TW.q); wid /= TW.q;
-  const int er = (int)(wid % a.mix_eh); wid /= a.mix_eh;
-  const int n = (int)wid;
+  const int ct = (int)(blk % ctiles); blk /= ctiles;
+  const int vg = (int)(blk % a.mix_vgroups); blk /= a.mix_vgroups;
+  const int er = (int)(blk % a.mix_rows); blk /= a.mix_rows;
+  const int n = (int)blk;
   if (n >= a.planes_n) return;
-  const int eh = a.mix_eh0 + er;                       // extended row
+  const int eh = a.mix_r0 + er;                        // extended row
   const int rh = fwd::mod_pos(eh, TH.q), uh = (eh - rh) / TH.q;
   const int c0 = ct * kDxgC;
-  const int v0 = a.mix_v0 + vc * kDxgV;                // first v of the wave
-  const uint16_t* const dyc = a.mix_dyc;
-  const uint16_t* const wpk = a.mix_wpk;
-  const int64_t rowstride = (int64_t)a.Wo * a.mix_opad;   // dyc row (16-bit units)
+  const int opad = a.mix_opad, nst = opad / kDxgO;
+  const int qw = TW.q;
+  const int vbase = a.mix_v0 + vg * a.mix_kw * 16 * MTN;   // first v of the workgroup
+  const int ncols = qw * a.mix_kw * 16 * MTN;              // extended columns of the workgroup
+  const int64_t drow = (int64_t)TW.p * nst * a.mix_dcells * kDxgO;   // dyc row (16-bit units)
+  const uint16_t* const dycn = a.mix_dyc + (int64_t)n * a.Ho * drow;
+  const bool zero_pad = a.pad == FCFS_PAD_ZERO;
+  const bool row_in = eh >= 0 && eh < a.H;
+  const bool row_zone = eh < a.mix_top || eh >= a.H - a.mix_bot;
+  const int vlim = a.mix_v0 + a.mix_vw;
+  const bool lds_epi = a.mix_lds_epi != 0;
 
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // height entries whose dy row exists
+  const int hs = a.mix_hl_start[rh], he = a.mix_hl_start[rh + 1];
+  auto h_ok = [&](int k) {
+    const int mh = uh - ((a.mix_hl[k] >> 7) - 64);
+    return mh >= 0 && mh < a.Mh;
+  };
+  int hfirst = hs, hcount = 0;
+  while (hfirst < he && !h_ok(hfirst)) ++hfirst;
+  for (int k = hfirst; k < he; ++k) hcount += h_ok(k) ? 1 : 0;
 
-  // positions of this lane's A rows (extended column q_w v + rw, v = v0 + 16 mt + li)
-  int vv[4];
-  bool vin[4];
+  for (int slot = wave; slot < qw * a.mix_kw; slot += 4) {
+    const int rw = slot % qw, kc = slot / qw;
+    const int vb = vbase + kc * 16 * MTN;                // first v of the wave
+    if (vb >= vlim) continue;
+    const int ws = a.mix_wl_start[rw], we = a.mix_wl_start[rw + 1];
+    // lane parts of the fragment offsets: A cell dleft + v (+ step's - dw),
+    // outputs 8 g4 ..; B channel c0 + li (+ 16 nt), outputs 8 g4 ..
+    uint32_t aoff[MTN];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    vv[mt] = v0 + 16 * mt + li;
-    const int ew = TW.q * vv[mt] + rw;
-    vin[mt] = ew >= a.mix_ew0 && ew <= a.mix_ew1;
-  }
-  const int nsteps = a.mix_opad / kDxgO;
-  for (int jh = 0; jh < TH.p; ++jh)
-    for (int ta = 0; ta < 4; ++ta) {
-      const int dh4 = TH.off[jh] + ta - rh;
-      if (fwd::mod_pos(dh4, TH.q) != 0) continue;
-      const int mh = uh - dh4 / TH.q;                    // exact division
-      if (mh < 0 || mh >= a.Mh) continue;
-      const uint16_t* const dyrow = dyc + ((int64_t)n * a.Ho + TH.p * mh + jh) * rowstride;
-      for (int jw = 0; jw < TW.p; ++jw)
-        for (int tb = 0; tb < 4; ++tb) {
-          const int dw4 = TW.off[jw] + tb - rw;
-          if (fwd::mod_pos(dw4, TW.q) != 0) continue;
-          const int dq = dw4 / TW.q;
-          // A rows: dy column p_w (v - dq) + jw, valid for 0 <= v - dq < Mw
-          int64_t aoff[4];
-          bool aok[4];
+    for (int mt = 0; mt < MTN; ++mt) aoff[mt] = (uint32_t)((a.mix_dleft + vb + 16 * mt + li) * kDxgO + 8 * g4);
+    const uint32_t boff = (uint32_t)((g4 * a.mix_cpad + c0 + li) * 8);
+
+    f32x4 acc[MTN][4];
 #pragma unroll
-          for (int mt = 0; mt < 4; ++mt) {
-            const int mw = vv[mt] - dq;
-            aok[mt] = vin[mt] && mw >= 0 && mw < a.Mw;
-            aoff[mt] = aok[mt] ? (int64_t)(TW.p * mw + jw) * a.mix_opad + 8 * g4 : 0;
-          }
-          const uint16_t* const wrow =
-              wpk + ((((int64_t)jh * TW.p + jw) * 16 + ta * 4 + tb) * a.mix_cpad + c0 + li) * a.mix_opad + 8 * g4;
-          for (int os = 0; os < nsteps; ++os) {
-            u16x8 af[4], bf[4];
+    for (int mt = 0; mt < MTN; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-              const u16x8 v = *reinterpret_cast<const u16x8*>(dyrow + aoff[mt] + kDxgO * os);
-              af[mt] = aok[mt] ? v : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-            }
+      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // steps (height entry hi, width entry wi, 32 outputs os)
+    const int steps = hcount * (we - ws) * nst;
+    int hi = hfirst, wi = ws, os = 0;
+    auto advance = [&]() {
+      if (++os < nst) return;
+      os = 0;
+      if (++wi < we) return;
+      wi = ws;
+      do ++hi;
+      while (hi < he && !h_ok(hi));
+    };
+    u16x8 af0[MTN], bf0[4], af1[MTN], bf1[4];
+    auto load = [&](u16x8 (&A)[MTN], u16x8 (&B)[4]) __attribute__((always_inline)) {
+      const int he_ = a.mix_hl[hi], we_ = a.mix_wl[wi];
+      const int jh = he_ & 31, ta = (he_ >> 5) & 3, mh = uh - ((he_ >> 7) - 64);
+      const int jw = we_ & 31, tb = (we_ >> 5) & 3, dw = (we_ >> 7) - 64;
+      const uint16_t* const ab =
+          dycn + (int64_t)(TH.p * mh + jh) * drow + ((int64_t)(jw * nst + os) * a.mix_dcells - dw) * kDxgO;
+      const uint16_t* const bb =
+          a.mix_wpk + ((((int64_t)jh * TW.p + jw) * 16 + ta * 4 + tb) * nst + os) * 4 * a.mix_cpad * 8;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-              bf[nt] = *reinterpret_cast<const u16x8*>(wrow + (int64_t)16 * nt * a.mix_opad + kDxgO * os);
+      for (int mt = 0; mt < MTN; ++mt) A[mt] = *reinterpret_cast<const u16x8*>(ab + aoff[mt]);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+      for (int nt = 0; nt < 4; ++nt) B[nt] = *reinterpret_cast<const u16x8*>(bb + boff + 16 * 8 * nt);
+      advance();
+    };
+    auto mma = [&](const u16x8 (&A)[MTN], const u16x8 (&B)[4]) __attribute__((always_inline)) {
 #pragma unroll
-              for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = M::mma(af[mt], bf[nt], acc[mt][nt]);
+      for (int mt = 0; mt < MTN; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = M::mma(A[mt], B[nt], acc[mt][nt]);
+    };
+    // two register buffers: step s + 1's fragments load during step s's MFMAs
+    if (steps > 0) load(af0, bf0);
+    for (int s = 0; s + 1 < steps; s += 2) {
+      load(af1, bf1);                      // step s + 1
+      mma(af0, bf0);                       // step s
+      if (s + 2 < steps) load(af0, bf0);   // step s + 2
+      mma(af1, bf1);                       // step s + 1
+    }
+    if (steps & 1) mma(af0, bf0);          // the last step
+
+    // slot epilogue: lane (c = c0 + 16 nt + li) holds v = vb + 16 mt + 4 g4 + i.
+    // Fold-zone and margin positions go to the edge buffer; the others are
+    // rounded into the LDS row tile (or, without it, stored directly).
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int cl = 16 * nt + li, c = c0 + cl;
+      const int64_t pc = (int64_t)n * a.C + c;
+#pragma unroll
+      for (int mt = 0; mt < MTN; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int v = vb + 16 * mt + 4 * g4 + i;
+          const int ew = qw * v + rw;
+          const float z = acc[mt][nt][i];
+          const bool direct = zero_pad || (!row_zone && ew >= a.mix_cl && ew < a.W - a.mix_cr);
+          if (lds_epi) otile[cl * ncols + (ew - qw * vbase)] = Mfma<DT>::to_store(z);
+          if (c >= a.C || v >= vlim) continue;
+          if (!direct) {
+            a.mix_edge[edge_index(a, pc, eh, ew)] = z;
+          } else if (!lds_epi && row_in && ew >= 0 && ew < a.W) {
+            S::store(reinterpret_cast<TS*>(a.dx) + (pc * a.H + eh) * a.W + ew, z);
           }
         }
     }
-  // z[n][c][er][rw][v - v0_all] (rows of mix_vpitch, a multiple of 4, so the
-  // 4 positions of a lane are one aligned 16-byte store): lane (c = c0 +
-  // 16 nt + li) holds v = v0 + 16 mt + 4 g4 + i
-  const int64_t zrow = (int64_t)TW.q * a.mix_vpitch;
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int c = c0 + 16 * nt + li;
-    if (c >= a.C) continue;
-    float* const zp = a.mix_z + (((int64_t)n * a.C + c) * a.mix_eh + er) * zrow + (int64_t)rw * a.mix_vpitch;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      const int vr = v0 + 16 * mt + 4 * g4 - a.mix_v0;
-      if (vr < a.mix_vpitch) *reinterpret_cast<f32x4*>(zp + vr) = acc[mt][nt];
+  }
+  if (!lds_epi || !row_in) return;
+  __syncthreads();
+  // the row segment [q_w vbase, q_w vbase + ncols) of each channel, 256
+  // consecutive columns per pass
+  const int e0 = qw * vbase;
+  for (int cl = 0; cl < kDxgC; ++cl) {
+    const int c = c0 + cl;
+    if (c >= a.C) break;
+    TS* const dxr = reinterpret_cast<TS*>(a.dx) + (((int64_t)n * a.C + c) * a.H + eh) * a.W;
+    for (int k = threadIdx.x; k < ncols; k += kThreads) {
+      const int ew = e0 + k;
+      if (ew < 0 || ew >= a.W) continue;
+      if (!zero_pad && (row_zone || ew < a.mix_cl || ew >= a.W - a.mix_cr)) continue;
+      if (ew >= qw * vlim) continue;
+      reinterpret_cast<uint16_t*>(dxr)[ew] = otile[cl * ncols + k];
     }
   }
 }
 
-// dx[n][c][i][j] = sum of z over the extended positions the padding maps to
-// (i, j) (itself, and for replicate / reflect the margin positions copying
-// it), in a fixed order, rounded once to the storage type.
+// dx at the samples the pad adjoint folds: the sum of z over the extended
+// positions the padding maps to (i, j), in ascending order, rounded once.
 template <int DT>
-__global__ __launch_bounds__(kThreads) void dx_mix_fold_kernel(const BwdArgs a) {
+__global__ __launch_bounds__(kThreads) void dx_mix_edge_kernel(const BwdArgs a) {
   using S = Store<DT>;
-  const AxisTable& TH = a.th;
-  const AxisTable& TW = a.tw_tab;
-  int64_t blk = blockIdx.x;
-  const int cb = (int)(blk % a.col_blocks); blk /= a.col_blocks;
-  const int i = (int)(blk % a.H);
-  const int64_t pc = blk / a.H;   // n * C + c
-  const int j = cb * kThreads + threadIdx.x;
-  if (j >= a.W) return;
-  const int64_t zrow = (int64_t)TW.q * a.mix_vpitch;
-  const float* const zp = a.mix_z + pc * a.mix_eh * zrow;
-  auto zat = [&](int eh, int ew) -> float {
-    const int rw = fwd::mod_pos(ew, TW.q), v = (ew - rw) / TW.q;
-    return zp[(int64_t)(eh - a.mix_eh0) * zrow + (int64_t)rw * a.mix_vpitch + (v - a.mix_v0)];
-  };
-  // The extended positions that map to (i, j), in ascending order. Only
-  // samples within the margins' reach of an edge (or every sample of a short
-  // axis, which a reflection may wrap around) can receive folded terms.
-  const int lm_w = -a.mix_ew0, rm_w = a.mix_ew1 - (a.W - 1);   // margins beyond the edges
-  const int lm_h = -a.mix_eh0, rm_h = a.mix_eh0 + a.mix_eh - a.H;
-  const bool zone_w = a.pad != FCFS_PAD_ZERO && (j <= lm_w || j >= a.W - 1 - rm_w || a.W <= lm_w + rm_w + 2);
-  const bool zone_h = a.pad != FCFS_PAD_ZERO && (i <= lm_h || i >= a.H - 1 - rm_h || a.H <= lm_h + rm_h + 2);
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (g >= (int64_t)a.planes_n * a.C * a.mix_edge_per) return;
+  const int64_t pc = g / a.mix_edge_per;
+  int64_t t = g - pc * a.mix_edge_per;
+  int i, j;
+  const int zr = a.mix_top + a.mix_bot;
+  if (t < (int64_t)zr * a.W) {
+    const int k = (int)(t / a.W);
+    j = (int)(t - (int64_t)k * a.W);
+    i = k < a.mix_top ? k : a.H - a.mix_bot + (k - a.mix_top);
+  } else {
+    t -= (int64_t)zr * a.W;
+    const int zc = a.mix_cl + a.mix_cr;
+    const int k = (int)(t / zc), m = (int)(t - (int64_t)k * zc);
+    i = a.mix_top + k;
+    j = m < a.mix_cl ? m : a.W - a.mix_cr + (m - a.mix_cl);
+  }
   float s = 0.f;
   auto add_row = [&](int eh) {
-    if (zone_w)
-      for (int ew = a.mix_ew0; ew < 0; ++ew)
-        if (pad_source(ew, a.W, a.pad) == j) s += zat(eh, ew);
-    s += zat(eh, j);
-    if (zone_w)
-      for (int ew = a.W; ew <= a.mix_ew1; ++ew)
-        if (pad_source(ew, a.W, a.pad) == j) s += zat(eh, ew);
+    for (int ew = a.mix_ew0; ew < 0; ++ew)
+      if (pad_source(ew, a.W, a.pad) == j) s += a.mix_edge[edge_index(a, pc, eh, ew)];
+    s += a.mix_edge[edge_index(a, pc, eh, j)];
+    for (int ew = a.W; ew <= a.mix_ew1; ++ew)
+      if (pad_source(ew, a.W, a.pad) == j) s += a.mix_edge[edge_index(a, pc, eh, ew)];
   };
-  if (zone_h)
-    for (int eh = a.mix_eh0; eh < 0; ++eh)
-      if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
+  for (int eh = a.mix_eh0; eh < 0; ++eh)
+    if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
   add_row(i);
-  if (zone_h)
-    for (int eh = a.H; eh < a.mix_eh0 + a.mix_eh; ++eh)
-      if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
-  (void)TH;
-  S::store(reinterpret_cast<typename S::T*>(a.dx) + pc * a.H * a.W + (int64_t)i * a.W + j, s);
+  for (int eh = a.H; eh <= a.mix_eh1; ++eh)
+    if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
+  S::store(reinterpret_cast<typename S::T*>(a.dx) + (pc * a.H + i) * a.W + j, s);
 }
 
 constexpr int kDwOuts = 32;   // outputs per weight-gradient workgroup (2 M tiles)
@@ -570,24 +681,235 @@ __global__ __launch_bounds__(kThreads) void dw_mix_reduce_kernel(const BwdArgs a
   a.dw[e] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Weight gradient on MFMA from two re-laid-out operands. For phase (jh, jw)
+// and tap (a, b),
+//   dW[jh][jw][o][c][a][b] = sum over cells (n, mh, mw) of
+//     dy[n][o][p_h mh + jh][p_w mw + jw] * ext(x)[n][c][q_h mh + off_h(jh) + a][q_w mw + s],
+// s = off_w(jw) + b: a GEMM with rows M = outputs, columns N = input
+// channels and the cells as the reduction K. Its fragments need 8
+// consecutive cells per lane, so two passes first lay out
+//   dyw[n][ho][jw][mw / 32][mw % 32 / 8][o][mw % 8]  (dy's cells of one phase), and
+//   xa[n][row][s][mw / 32][mw % 32 / 8][c][mw % 8]   (ext(x) at column q_w mw + s,
+//                                                     padding resolved, every tap offset s),
+// so that a fragment (16 outputs or channels x 32 cells) is four 256-byte
+// runs, one 16-byte load per lane. A workgroup takes one phase, one tap row a,
+// 64 outputs, 64 channels and a chunk of cell rows; wave b takes tap column b
+// (the four waves read the same dy fragments and share them in L1), with the
+// next step's fragments in flight during the current step's MFMAs. The
+// chunks' partial sums are added in chunk order by a last pass.
+constexpr int kDwgT = 64;    // outputs and channels per workgroup tile (4 x 4 MFMA tiles)
+constexpr int kDwyPitch = 258;   // LDS pitch (16-bit units) of the dy pass tile: 256 columns + 2
+
+// dyw from dy: a block takes 64 outputs of one output row and dwcells cells
+// (all p_w phases: at most 256 columns) through an LDS tile [o][column].
+__global__ __launch_bounds__(kThreads) void dw_mix_dy_kernel(const BwdArgs a) {
+  extern __shared__ float smem[];
+  uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
+  const int pw = a.tw_tab.p;
+  const int bc = a.mix_dwcells;                     // cells per block (multiple of 8)
+  const int cblocks = (a.mix_ncb * 32 + bc - 1) / bc;
+  const int oblocks = a.mix_dwopad / 64;
+  int64_t blk = blockIdx.x;
+  const int ob = (int)(blk % oblocks); blk /= oblocks;
+  const int cbk = (int)(blk % cblocks); blk /= cblocks;
+  const int ho = (int)(blk % a.Ho);
+  const int n = (int)(blk / a.Ho);
+  const int mw0 = cbk * bc, o0 = ob * 64;
+  const int ncols = bc * pw;
+  const uint16_t* const dyb = reinterpret_cast<const uint16_t*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo + (int64_t)ho * a.Wo;
+  const int64_t oplane = (int64_t)a.Ho * a.Wo;
+  for (int it = threadIdx.x; it < 64 * ncols; it += kThreads) {
+    const int col = it % ncols, r = it / ncols;
+    const int wo = mw0 * pw + col, o = o0 + r;
+    tile[r * kDwyPitch + col] = (wo < a.Wo && o < a.Cout) ? dyb[(int64_t)o * oplane + wo] : 0;
+  }
+  __syncthreads();
+  // chunks (jw, 8 cells g, output o), o fastest: 16 bytes of 8 cells each
+  const int ng = bc / 8;
+  uint16_t* const orow = a.mix_dyw + ((int64_t)n * a.Ho + ho) * pw * a.mix_ncb * 32 * a.mix_dwopad;
+  for (int e = threadIdx.x; e < pw * ng * 64; e += kThreads) {
+    const int o = e % 64, gb = (e / 64) % ng, jw = e / (64 * ng);
+    const int mw = mw0 + 8 * gb;
+    if (mw >= a.mix_ncb * 32) continue;
+    u16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = tile[o * kDwyPitch + pw * (8 * gb + i) + jw];
+    *reinterpret_cast<u16x8*>(orow + ((((int64_t)jw * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_dwopad + o0 + o) * 8) = v;
+  }
+}
+
+// xa from x: a block takes 64 channels of one extended row and dwxcells
+// cells, reading the input columns those cells' taps reach (padding resolved)
+// into an LDS tile [c][column].
+constexpr int kDwxPitch = 306;   // LDS pitch (16-bit units) of the x pass tile
+__global__ __launch_bounds__(kThreads) void dw_mix_x_kernel(const BwdArgs a) {
+  extern __shared__ float smem[];
+  uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
+  const int q = a.tw_tab.q;
+  const int bc = a.mix_dwxcells;
+  const int cblocks = (a.mix_ncb * 32 + bc - 1) / bc;
+  const int chunks = a.mix_cpad / 64;
+  const int erows = a.mix_eh1 - a.mix_eh0 + 1;
+  int64_t blk = blockIdx.x;
+  const int cc = (int)(blk % chunks); blk /= chunks;
+  const int cbk = (int)(blk % cblocks); blk /= cblocks;
+  const int er = (int)(blk % erows); blk /= erows;
+  const int n = (int)blk;
+  const int mw0 = cbk * bc, c0 = cc * 64;
+  const int ns = a.mix_ns;
+  const int col0 = q * mw0 + a.mix_s0;
+  const int ncols = q * (bc - 1) + ns;   // <= kDwxPitch - 2
+  const int sr = pad_source(a.mix_eh0 + er, a.H, a.pad);
+  const uint16_t* const xb = reinterpret_cast<const uint16_t*>(a.x) + (int64_t)n * a.C * a.H * a.W;
+  for (int it = threadIdx.x; it < 64 * ncols; it += kThreads) {
+    const int t = it % ncols, r = it / ncols;
+    const int sc = pad_source(col0 + t, a.W, a.pad), c = c0 + r;
+    tile[r * kDwxPitch + t] = (sr >= 0 && sc >= 0 && c < a.C) ? xb[((int64_t)c * a.H + sr) * a.W + sc] : 0;
+  }
+  __syncthreads();
+  const int ng = bc / 8;
+  uint16_t* const orow = a.mix_xa + ((int64_t)n * erows + er) * ns * a.mix_ncb * 32 * a.mix_cpad;
+  for (int e = threadIdx.x; e < ns * ng * 64; e += kThreads) {
+    const int c = e % 64, gb = (e / 64) % ng, s = e / (64 * ng);
+    const int mw = mw0 + 8 * gb;
+    if (mw >= a.mix_ncb * 32) continue;
+    u16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (mw + i < a.Mw) ? tile[c * kDwxPitch + q * (8 * gb + i) + s] : (uint16_t)0;
+    *reinterpret_cast<u16x8*>(orow + ((((int64_t)s * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_cpad + c0 + c) * 8) = v;
+  }
+}
+
+// Partial sums of one chunk of cell rows: partial[chunk][ph][tap][o][c].
+template <int DT>
+__global__ __launch_bounds__(kThreads, 2) void dw_mix_gemm_kernel(const BwdArgs a) {
+  using M = Mfma<DT>;
+  const AxisTable& TH = a.th;
+  const AxisTable& TW = a.tw_tab;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, g4 = lane >> 4;
+  const int tb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t blk = bwd::xcd_block();
+  const int ctiles = a.mix_cpad / kDwgT, otiles = a.mix_dwopad / kDwgT;
+  const int ct = (int)(blk % ctiles); blk /= ctiles;
+  const int ot = (int)(blk % otiles); blk /= otiles;
+  const int ta = (int)(blk % 4); blk /= 4;
+  const int ph = (int)(blk % (TH.p * TW.p)); blk /= TH.p * TW.p;
+  const int chunk = (int)blk;
+  if (chunk >= a.mix_wchunks) return;
+  const int jh = ph / TW.p, jw = ph % TW.p;
+  const int s = TW.off[jw] + tb - a.mix_s0;
+  const int erows = a.mix_eh1 - a.mix_eh0 + 1;
+  const int ncb = a.mix_ncb;
+  const int G = a.planes_n * a.Mh;   // cell rows (n, mh)
+  const int g_lo = (int)((int64_t)G * chunk / a.mix_wchunks);
+  const int g_hi = (int)((int64_t)G * (chunk + 1) / a.mix_wchunks);
+  const int64_t ystride = (int64_t)4 * a.mix_dwopad * 8;   // one 32-cell block of dyw
+  const int64_t xstride = (int64_t)4 * a.mix_cpad * 8;     // one 32-cell block of xa
+  const uint32_t aoff = (uint32_t)((g4 * a.mix_dwopad + ot * kDwgT + li) * 8);
+  const uint32_t boff = (uint32_t)((g4 * a.mix_cpad + ct * kDwgT + li) * 8);
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int steps = (g_hi - g_lo) * ncb;
+  int g = g_lo, cb = 0;
+  const uint16_t *yrow = nullptr, *xrow = nullptr;
+  auto set_row = [&]() {
+    const int n = g / a.Mh, mh = g - n * a.Mh;
+    const int ho = TH.p * mh + jh, er = TH.q * mh + TH.off[jh] + ta - a.mix_eh0;
+    yrow = a.mix_dyw + (((int64_t)n * a.Ho + ho) * TW.p + jw) * ncb * ystride;
+    xrow = a.mix_xa + (((int64_t)n * erows + er) * a.mix_ns + s) * ncb * xstride;
+  };
+  if (steps > 0) set_row();
+  u16x8 af0[4], bf0[4], af1[4], bf1[4];
+  auto load = [&](u16x8 (&A)[4], u16x8 (&B)[4]) __attribute__((always_inline)) {
+    const uint16_t* const ab = yrow + cb * ystride;
+    const uint16_t* const bb = xrow + cb * xstride;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) A[mt] = *reinterpret_cast<const u16x8*>(ab + aoff + 16 * 8 * mt);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) B[nt] = *reinterpret_cast<const u16x8*>(bb + boff + 16 * 8 * nt);
+    if (++cb == ncb) {
+      cb = 0;
+      if (++g < g_hi) set_row();
+    }
+  };
+  auto mma = [&](const u16x8 (&A)[4], const u16x8 (&B)[4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = M::mma(A[mt], B[nt], acc[mt][nt]);
+  };
+  if (steps > 0) load(af0, bf0);
+  for (int st = 0; st + 1 < steps; st += 2) {
+    load(af1, bf1);
+    mma(af0, bf0);
+    if (st + 2 < steps) load(af0, bf0);
+    mma(af1, bf1);
+  }
+  if (steps & 1) mma(af0, bf0);
+
+  // D: lane holds column c = 16 nt + li, rows o = 16 mt + 4 g4 + r
+  float* const out = a.partial + (((int64_t)chunk * TH.p * TW.p + ph) * 16 + ta * 4 + tb) * a.Cout * a.C;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = ot * kDwgT + 16 * mt + 4 * g4 + r, c = ct * kDwgT + 16 * nt + li;
+        if (o < a.Cout && c < a.C) out[(int64_t)o * a.C + c] = acc[mt][nt][r];
+      }
+}
+
+// dw[ph][o][c][tap] = sum of the chunks' partial[chunk][ph][tap][o][c], in
+// chunk order (threads run over the partials' order, so the reads coalesce).
+__global__ __launch_bounds__(kThreads) void dw_mix_gemm_reduce_kernel(const BwdArgs a) {
+  const int64_t oc = (int64_t)a.Cout * a.C;
+  const int64_t per = (int64_t)a.th.p * a.tw_tab.p * 16 * oc;
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= per) return;
+  float s = 0.f;
+  for (int k = 0; k < a.mix_wchunks; ++k) s += a.partial[k * per + e];
+  const int64_t r = e % oc, pt = e / oc;
+  const int tap = (int)(pt % 16);
+  const int64_t ph = pt / 16;
+  a.dw[(ph * oc + r) * 16 + tap] = s;
+}
+
 template <int DT>
 fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
   const dim3 block(kThreads);
   hipLaunchKernelGGL((bwd::adjoint_tables_kernel<DT>), dim3((unsigned)(((int64_t)a.H + a.W + kThreads - 1) / kThreads)),
                      block, 0, stream, a);
   if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
-  if (a.dx && a.mix_z) {
-    // channel-last dy, packed weights, z on MFMA, then the fold
-    const int64_t cl_blocks = (int64_t)a.planes_n * a.Ho * ((a.Wo + 63) / 64);
+  if (a.dx && a.mix_dyc) {
+    // channel-last dy, packed weights, z on MFMA (dx directly, the fold zones
+    // to the edge buffer), then the fold zones
+    const int64_t cl_blocks = (int64_t)a.planes_n * a.Ho * ((a.mix_dcells + a.mix_clcells - 1) / a.mix_clcells);
     hipLaunchKernelGGL(dx_mix_channel_last_kernel, dim3((unsigned)cl_blocks), block,
-                       sizeof(uint16_t) * 64 * kDxcPitch, stream, a);
+                       sizeof(uint16_t) * 128 * kDxcPitch, stream, a);
     const int64_t wtotal = (int64_t)a.th.p * a.tw_tab.p * 16 * a.mix_cpad * a.mix_opad;
     hipLaunchKernelGGL(dx_mix_pack_weights_kernel, dim3((unsigned)((wtotal + kThreads - 1) / kThreads)), block, 0,
                        stream, a);
-    const int64_t waves = (int64_t)a.planes_n * a.mix_eh * a.tw_tab.q * a.mix_vchunks * (a.mix_cpad / kDxgC);
-    hipLaunchKernelGGL((dx_mix_gemm_kernel<DT>), dim3((unsigned)((waves + 3) / 4)), block, 0, stream, a);
-    const int64_t fblocks = (int64_t)a.planes_n * a.C * a.H * a.col_blocks;
-    hipLaunchKernelGGL((dx_mix_fold_kernel<DT>), dim3((unsigned)fblocks), block, 0, stream, a);
+    const int64_t gblocks = (int64_t)a.planes_n * a.mix_rows * a.mix_vgroups * (a.mix_cpad / kDxgC);
+    const dim3 ggrid((unsigned)gblocks);
+    const size_t glds = a.mix_lds_epi ? sizeof(uint16_t) * kDxgC * a.tw_tab.q * a.mix_kw * 16 * a.mix_mtn : 0;
+    switch (a.mix_mtn) {
+      case 1: hipLaunchKernelGGL((dx_mix_gemm_kernel<DT, 1>), ggrid, block, glds, stream, a); break;
+      case 2: hipLaunchKernelGGL((dx_mix_gemm_kernel<DT, 2>), ggrid, block, glds, stream, a); break;
+      case 3: hipLaunchKernelGGL((dx_mix_gemm_kernel<DT, 3>), ggrid, block, glds, stream, a); break;
+      default: hipLaunchKernelGGL((dx_mix_gemm_kernel<DT, 4>), ggrid, block, glds, stream, a); break;
+    }
+    if (a.mix_edge) {
+      const int64_t eblocks = ((int64_t)a.planes_n * a.C * a.mix_edge_per + kThreads - 1) / kThreads;
+      if (eblocks > 0) hipLaunchKernelGGL((dx_mix_edge_kernel<DT>), dim3((unsigned)eblocks), block, 0, stream, a);
+    }
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   } else if (a.dx) {
     const int64_t blocks = (int64_t)a.planes_n * a.H * a.col_blocks * a.mix_cblocks;
@@ -595,7 +917,21 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL((dx_mix_kernel<DT>), dim3((unsigned)blocks), block, lds, stream, a);
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }
-  if (a.dw) {
+  if (a.dw && a.mix_dyw) {
+    // dy by phase, x by tap offset, the GEMM per (phase, tap row) and chunk,
+    // then the chunks added in order
+    const int64_t ncb32 = (int64_t)a.mix_ncb * 32;
+    const int64_t yblocks = (int64_t)a.planes_n * a.Ho * ((ncb32 + a.mix_dwcells - 1) / a.mix_dwcells) * (a.mix_dwopad / 64);
+    hipLaunchKernelGGL(dw_mix_dy_kernel, dim3((unsigned)yblocks), block, sizeof(uint16_t) * 64 * kDwyPitch, stream, a);
+    const int64_t erows = a.mix_eh1 - a.mix_eh0 + 1;
+    const int64_t xblocks = (int64_t)a.planes_n * erows * ((ncb32 + a.mix_dwxcells - 1) / a.mix_dwxcells) * (a.mix_cpad / 64);
+    hipLaunchKernelGGL(dw_mix_x_kernel, dim3((unsigned)xblocks), block, sizeof(uint16_t) * 64 * kDwxPitch, stream, a);
+    const int64_t gblocks = (int64_t)a.mix_wchunks * a.th.p * a.tw_tab.p * 4 * (a.mix_dwopad / kDwgT) * (a.mix_cpad / kDwgT);
+    hipLaunchKernelGGL((dw_mix_gemm_kernel<DT>), dim3((unsigned)gblocks), block, 0, stream, a);
+    const int64_t per = (int64_t)a.th.p * a.tw_tab.p * 16 * a.Cout * a.C;
+    hipLaunchKernelGGL(dw_mix_gemm_reduce_kernel, dim3((unsigned)((per + kThreads - 1) / kThreads)), block, 0, stream, a);
+    if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
+  } else if (a.dw) {
     const int64_t blocks = (int64_t)a.th.p * a.tw_tab.p * a.mix_otiles * a.mix_ctiles * a.mix_kchunks;
     const size_t lds = sizeof(float) * 4 * kDwOuts * 128;   // >= the staging (4 x 11 KB)
     if (a.tw_tab.q <= 4) hipLaunchKernelGGL((dw_mix_partial_kernel<DT, true>), dim3((unsigned)blocks), block, lds, stream, a);

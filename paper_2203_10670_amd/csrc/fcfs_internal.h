@@ -102,16 +102,40 @@ struct BwdArgs {
   const void* mix_weight;  // [p_h][p_w][Cout][C][4][4], 16-bit storage
   int mix_cblocks;         // input-gradient workgroups per row block: ceil(C / 32)
   int mix_otiles, mix_ctiles, mix_kchunks;   // weight gradient: 32 outputs x 8 channels x chunks of cell rows
-  // input gradient on MFMA (workspace): channel-last dy, packed weights, and
-  // z = C^T dy over the extended positions [eh0, eh0 + eh) x [ew0, ew1],
-  // stored [n][c][row][width class][v - v0] (v0 .. v0 + vw - 1)
-  uint16_t* mix_dyc;       // [n][ho][wo][opad]
-  uint16_t* mix_wpk;       // [p_h][p_w][4][4][cpad][opad]
-  float* mix_z;            // null: the input gradient runs on the vector ALUs
+  // input gradient on MFMA (workspace): channel-last dy with zero margin
+  // cells, packed weights, and the edge buffer of the pad adjoint
+  uint16_t* mix_dyc;       // [n][ho][p_w][opad / 32][dcells][32]: dy[o][ho][p_w mw + jw] at cell dleft + mw
+  uint16_t* mix_wpk;       // [p_h][p_w][4][4][opad / 32][4][cpad][8]: W[o][c] at (o / 32, o % 32 / 8, c, o % 8)
+  float* mix_edge;         // z at the positions the pad adjoint folds (null for zero padding)
   int mix_opad, mix_cpad;  // C_out rounded up to 32, C_in rounded up to 64
-  int mix_eh0, mix_eh, mix_ew0, mix_ew1, mix_v0, mix_vw, mix_vpitch, mix_vchunks;   // vpitch: vw rounded up to 4
-  int mix_dx_gemm;         // the grids fit: the input gradient on MFMA
-  size_t mix_ws_dyc, mix_ws_wpk, mix_ws_z;   // workspace offsets of the three buffers
+  int mix_dleft, mix_dcells;                // margin cells left of cell 0; cells per phase row
+  int mix_clcells;                          // cells per block of the channel-last pass (<= 128 columns)
+  int mix_eh0, mix_eh1, mix_ew0, mix_ew1;   // extended positions the taps read (inclusive)
+  int mix_r0, mix_rows;                     // extended rows of the GEMM: [r0, r0 + rows)
+  int mix_v0, mix_vw, mix_mtn, mix_vchunks; // width-class positions [v0, v0 + vw) in chunks of 16 mtn
+  int mix_kw, mix_vgroups;                  // chunks per workgroup (all width classes of each), groups per row
+  int mix_lds_epi;                          // the workgroup interleaves the classes in LDS (q_w * kw <= 8)
+  int mix_top, mix_bot, mix_cl, mix_cr;     // fold zones: rows [0, top), [H - bot, H); columns [0, cl), [W - cr, W)
+  int mix_rr, mix_cc;                       // edge buffer: zone rows (part R), zone columns (part C)
+  int64_t mix_edge_c;                       // floats of part R (part C follows)
+  int64_t mix_edge_per;                     // input samples per plane in a fold zone
+  int mix_dx_gemm;                          // the grids fit: the input gradient on MFMA
+  size_t mix_ws_dyc, mix_ws_wpk, mix_ws_edge;   // workspace offsets of the three buffers
+  // weight gradient on MFMA (workspace): dy by phase and x by tap column
+  // offset, 8 cells per 16-byte group; partial sums [chunk][ph][tap][o][c]
+  uint16_t* mix_dyw;       // [n][ho][p_w][ncb][4][dwopad][8]: dy[o][ho][p_w mw + jw] at mw = 32 block + 8 group + i
+  uint16_t* mix_xa;        // [n][row - eh0][s][ncb][4][cpad][8]: ext(x)[c][row][q_w mw + s0 + s]
+  int mix_dwopad, mix_ncb;        // C_out rounded up to 64; 32-cell blocks per cell row
+  int mix_s0, mix_ns;             // tap column offsets s0 .. s0 + ns - 1
+  int mix_dwcells, mix_dwxcells;  // cells per block of the dy and x passes
+  int mix_wchunks;                // chunks of cell rows
+  int mix_dw_gemm;                // the weight gradient on MFMA
+  size_t mix_ws_dyw, mix_ws_xa;
+  // (tap, d) of each residue r of the height / width axis: entries
+  // [start[r], start[r + 1]), each phase | tap << 5 | (d + 64) << 7, where
+  // the extended index q u + r reads cell u - d of that phase at that tap
+  int mix_hl_start[kMaxFactor + 1], mix_hl[4 * kMaxFactor];
+  int mix_wl_start[kMaxFactor + 1], mix_wl[4 * kMaxFactor];
   AxisTable th, tw_tab;
 };
 

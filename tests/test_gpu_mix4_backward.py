@@ -1,6 +1,7 @@
-"""GPU parity of the channel-mixing layer's backward (input gradient gathered
-over the adjoint tables, weight gradient on MFMA over cells) against the FP64
-oracle's adjoint, through the C ABI, plus the autograd wrapper on it."""
+"""GPU parity of the channel-mixing layer's backward (input gradient as an
+implicit GEMM on MFMA per residue class with the pad adjoint folded at the
+edges, weight gradient on MFMA over cells) against the FP64 oracle's adjoint,
+through the C ABI, plus the autograd wrapper on it."""
 import sys
 from math import gcd
 
@@ -27,6 +28,13 @@ CASES = [
     (7, 5, "reflect", "f16", (1, 5, 12, 33), 3),
     (1, 1, "zero", "bf16", (1, 64, 9, 64), 64),
     (4, 1, "reflect", "bf16", (1, 3, 5, 20), 70),
+    # first taps past the edge (q >= 3p): samples no tap reads get 0
+    (1, 8, "replicate", "bf16", (1, 4, 40, 75), 6),
+    (2, 7, "reflect", "f16", (1, 5, 30, 61), 4),
+    # axes short enough for every sample to take folded margins; 70 channels
+    # (two channel tiles of the GEMM)
+    (5, 4, "reflect", "bf16", (1, 3, 3, 5), 3),
+    (3, 2, "replicate", "bf16", (1, 70, 2, 9), 70),
 ]
 
 

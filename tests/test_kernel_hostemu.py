@@ -94,20 +94,29 @@ def test_copy_axis_beside_resampled_axis():
 
 
 def test_channel_mixing_backward():
-    # input gradient (gathered over the adjoint tables) and weight gradient
-    # (MFMA over cells, chunks added in order), 16-bit storage
+    # input gradient (implicit GEMM per residue class on MFMA, pad adjoint
+    # folded at the edges) and weight gradient (MFMA over cells, chunks added
+    # in order), 16-bit storage
     cases = []
     for i, (p, q, pad, dt, shape, cout) in enumerate([
             (5, 4, "reflect", "bf16", [2, 3, 9, 40], 5),
             (3, 2, "zero", "f16", [1, 9, 7, 35], 33),
-            # two column blocks, both columns of a thread live in the first
+            # first taps past the edge (q >= 3p): samples no tap reads get 0
+            (1, 8, "replicate", "bf16", [1, 2, 20, 37], 3),
+            # axes short enough for every sample to take folded margins
+            (5, 4, "reflect", "bf16", [1, 2, 3, 5], 3),
+            # several chunk groups per row
             (5, 4, "reflect", "bf16", [1, 3, 5, 700], 6),
             (2, 3, "replicate", "bf16", [1, 2, 11, 300], 3),
             (7, 5, "reflect", "bf16", [1, 33, 6, 21], 2),
-            # 8 width phases and several output tiles
+            (2, 7, "reflect", "bf16", [1, 3, 15, 30], 4),
+            (3, 2, "replicate", "f16", [1, 4, 2, 9], 70),
+            # 8 width phases and several output steps
             (8, 3, "zero", "bf16", [1, 4, 10, 100], 70),
-            (4, 7, "reflect", "f16", [1, 9, 17, 270], 20)]):
-        if ALL or i < 3:
+            (4, 7, "reflect", "f16", [1, 9, 17, 270], 20),
+            # q_w > 8: the classes are stored without the LDS row tile
+            (2, 11, "reflect", "bf16", [1, 2, 23, 50], 3)]):
+        if ALL or i < 4:
             cases.append({"mode": "bwd", "p": p, "q": q, "method": "mix4", "pad": pad, "dtype": dt, "shape": shape,
                           "cout": cout})
     _run(cases)
