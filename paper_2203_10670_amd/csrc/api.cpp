@@ -161,7 +161,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // The channel-mixing weight gradient as a GEMM over re-laid-out operands
 // (otherwise the per-phase staging kernel).
-constexpr bool kMixDwGemm = false;
+constexpr bool kMixDwGemm = true;
 
 // The (phase, tap) pairs of each residue class of an axis's extended index,
 // for the channel-mixing input gradient: e = q u + r is read by tap t of
