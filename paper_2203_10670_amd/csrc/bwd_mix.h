@@ -702,7 +702,10 @@ constexpr int kDwgT = 64;    // outputs and channels per workgroup tile (4 x 4 M
 constexpr int kDwyPitch = 258;   // LDS pitch (16-bit units) of the dy pass tile: 256 columns + 2
 
 // dyw from dy: a block takes 64 outputs of one output row and dwcells cells
-// (all p_w phases: at most 256 columns) through an LDS tile [o][column].
+// (all p_w phases: at most 256 columns) through an LDS tile [o][column]. Wave
+// w reads rows w, w + 4, ... of the tile (aligned column pairs when W_out is
+// even), then lane o gathers 8 cells of one phase from its row (the pitch
+// puts the 64 rows on distinct banks) and writes them as 16 bytes.
 __global__ __launch_bounds__(kThreads) void dw_mix_dy_kernel(const BwdArgs a) {
   extern __shared__ float smem[];
   uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
@@ -716,36 +719,74 @@ __global__ __launch_bounds__(kThreads) void dw_mix_dy_kernel(const BwdArgs a) {
   const int ho = (int)(blk % a.Ho);
   const int n = (int)(blk / a.Ho);
   const int mw0 = cbk * bc, o0 = ob * 64;
-  const int ncols = bc * pw;
+  const int ncols = bc * pw;                        // even (bc is)
+  const int wo0 = mw0 * pw;                         // even
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint16_t* const dyb = reinterpret_cast<const uint16_t*>(a.dy) + (int64_t)n * a.Cout * a.Ho * a.Wo + (int64_t)ho * a.Wo;
   const int64_t oplane = (int64_t)a.Ho * a.Wo;
-  for (int it = threadIdx.x; it < 64 * ncols; it += kThreads) {
-    const int col = it % ncols, r = it / ncols;
-    const int wo = mw0 * pw + col, o = o0 + r;
-    tile[r * kDwyPitch + col] = (wo < a.Wo && o < a.Cout) ? dyb[(int64_t)o * oplane + wo] : 0;
+  // rows wave + 4 i (16 per wave), all loads of a wave issued before its LDS stores
+  if ((a.Wo & 1) == 0 && (reinterpret_cast<uintptr_t>(a.dy) & 3) == 0) {
+    uint32_t v[16][2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = wave + 4 * i;
+      const bool ok = o0 + r < a.Cout;
+      const uint16_t* const src = dyb + (int64_t)(ok ? o0 + r : 0) * oplane;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int wo = wo0 + 2 * (lane + 64 * j);   // W_out even: wo + 1 < W_out when wo < W_out
+        v[i][j] = (ok && 2 * (lane + 64 * j) < ncols && wo < a.Wo) ? *reinterpret_cast<const uint32_t*>(src + wo) : 0u;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (2 * (lane + 64 * j) < ncols)
+          *reinterpret_cast<uint32_t*>(tile + (wave + 4 * i) * kDwyPitch + 2 * (lane + 64 * j)) = v[i][j];
+  } else {
+    uint16_t v[16][4];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = wave + 4 * i;
+      const bool ok = o0 + r < a.Cout;
+      const uint16_t* const src = dyb + (int64_t)(ok ? o0 + r : 0) * oplane;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = lane + 64 * j;
+        v[i][j] = (ok && t < ncols && wo0 + t < a.Wo) ? src[wo0 + t] : (uint16_t)0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (lane + 64 * j < ncols) tile[(wave + 4 * i) * kDwyPitch + lane + 64 * j] = v[i][j];
   }
   __syncthreads();
-  // chunks (jw, 8 cells g, output o), o fastest: 16 bytes of 8 cells each
   const int ng = bc / 8;
   uint16_t* const orow = a.mix_dyw + ((int64_t)n * a.Ho + ho) * pw * a.mix_ncb * 32 * a.mix_dwopad;
-  for (int e = threadIdx.x; e < pw * ng * 64; e += kThreads) {
-    const int o = e % 64, gb = (e / 64) % ng, jw = e / (64 * ng);
+  for (int k = wave; k < pw * ng; k += 4) {
+    const int jw = k / ng, gb = k - jw * ng;
     const int mw = mw0 + 8 * gb;
     if (mw >= a.mix_ncb * 32) continue;
     u16x8 v;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = tile[o * kDwyPitch + pw * (8 * gb + i) + jw];
-    *reinterpret_cast<u16x8*>(orow + ((((int64_t)jw * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_dwopad + o0 + o) * 8) = v;
+    for (int i = 0; i < 8; ++i) v[i] = tile[lane * kDwyPitch + pw * (8 * gb + i) + jw];
+    *reinterpret_cast<u16x8*>(orow + ((((int64_t)jw * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_dwopad + o0 + lane) * 8) = v;
   }
 }
 
 // xa from x: a block takes 64 channels of one extended row and dwxcells
-// cells, reading the input columns those cells' taps reach (padding resolved)
-// into an LDS tile [c][column].
+// cells, reading the input columns those cells' taps reach (padding resolved
+// once per column into LDS) into an LDS tile [c][column]; then lane c
+// gathers 8 cells of one tap offset from its row and writes them as 16 bytes.
 constexpr int kDwxPitch = 306;   // LDS pitch (16-bit units) of the x pass tile
 __global__ __launch_bounds__(kThreads) void dw_mix_x_kernel(const BwdArgs a) {
   extern __shared__ float smem[];
   uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
+  int* const scol = reinterpret_cast<int*>(tile + 64 * kDwxPitch);   // source column of each tile column
   const int q = a.tw_tab.q;
   const int bc = a.mix_dwxcells;
   const int cblocks = (a.mix_ncb * 32 + bc - 1) / bc;
@@ -760,24 +801,46 @@ __global__ __launch_bounds__(kThreads) void dw_mix_x_kernel(const BwdArgs a) {
   const int ns = a.mix_ns;
   const int col0 = q * mw0 + a.mix_s0;
   const int ncols = q * (bc - 1) + ns;   // <= kDwxPitch - 2
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sr = pad_source(a.mix_eh0 + er, a.H, a.pad);
+  for (int t = threadIdx.x; t < ncols; t += kThreads) scol[t] = pad_source(col0 + t, a.W, a.pad);
+  __syncthreads();
   const uint16_t* const xb = reinterpret_cast<const uint16_t*>(a.x) + (int64_t)n * a.C * a.H * a.W;
-  for (int it = threadIdx.x; it < 64 * ncols; it += kThreads) {
-    const int t = it % ncols, r = it / ncols;
-    const int sc = pad_source(col0 + t, a.W, a.pad), c = c0 + r;
-    tile[r * kDwxPitch + t] = (sr >= 0 && sc >= 0 && c < a.C) ? xb[((int64_t)c * a.H + sr) * a.W + sc] : 0;
+  // rows wave + 4 i in two batches of 8 per wave, all loads of a batch issued
+  // before its LDS stores
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint16_t v[8][5];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = wave + 4 * (8 * h + i);
+      const bool ok = sr >= 0 && c0 + r < a.C;
+      const uint16_t* const src = xb + ((int64_t)(ok ? c0 + r : 0) * a.H + (sr >= 0 ? sr : 0)) * a.W;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int t = lane + 64 * j;
+        const int sc = t < ncols ? scol[t] : -1;
+        v[i][j] = (ok && sc >= 0) ? src[sc] : (uint16_t)0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+        if (lane + 64 * j < ncols) tile[(wave + 4 * (8 * h + i)) * kDwxPitch + lane + 64 * j] = v[i][j];
   }
   __syncthreads();
   const int ng = bc / 8;
   uint16_t* const orow = a.mix_xa + ((int64_t)n * erows + er) * ns * a.mix_ncb * 32 * a.mix_cpad;
-  for (int e = threadIdx.x; e < ns * ng * 64; e += kThreads) {
-    const int c = e % 64, gb = (e / 64) % ng, s = e / (64 * ng);
+  for (int k = wave; k < ns * ng; k += 4) {
+    const int sidx = k / ng, gb = k - sidx * ng;
     const int mw = mw0 + 8 * gb;
     if (mw >= a.mix_ncb * 32) continue;
     u16x8 v;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = (mw + i < a.Mw) ? tile[c * kDwxPitch + q * (8 * gb + i) + s] : (uint16_t)0;
-    *reinterpret_cast<u16x8*>(orow + ((((int64_t)s * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_cpad + c0 + c) * 8) = v;
+    for (int i = 0; i < 8; ++i) v[i] = (mw + i < a.Mw) ? tile[lane * kDwxPitch + q * (8 * gb + i) + sidx] : (uint16_t)0;
+    *reinterpret_cast<u16x8*>(orow + ((((int64_t)sidx * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_cpad + c0 + lane) * 8) = v;
   }
 }
 
@@ -925,7 +988,8 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(dw_mix_dy_kernel, dim3((unsigned)yblocks), block, sizeof(uint16_t) * 64 * kDwyPitch, stream, a);
     const int64_t erows = a.mix_eh1 - a.mix_eh0 + 1;
     const int64_t xblocks = (int64_t)a.planes_n * erows * ((ncb32 + a.mix_dwxcells - 1) / a.mix_dwxcells) * (a.mix_cpad / 64);
-    hipLaunchKernelGGL(dw_mix_x_kernel, dim3((unsigned)xblocks), block, sizeof(uint16_t) * 64 * kDwxPitch, stream, a);
+    hipLaunchKernelGGL(dw_mix_x_kernel, dim3((unsigned)xblocks), block,
+                       sizeof(uint16_t) * 64 * kDwxPitch + sizeof(int) * kDwxPitch, stream, a);
     const int64_t gblocks = (int64_t)a.mix_wchunks * a.th.p * a.tw_tab.p * 4 * (a.mix_dwopad / kDwgT) * (a.mix_cpad / kDwgT);
     hipLaunchKernelGGL((dw_mix_gemm_kernel<DT>), dim3((unsigned)gblocks), block, 0, stream, a);
     const int64_t per = (int64_t)a.th.p * a.tw_tab.p * 16 * a.Cout * a.C;
