@@ -159,9 +159,6 @@ static int adjoint_cmax(const AxisTable& t, int n, int cells, int pad) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// The channel-mixing weight gradient as a GEMM over re-laid-out operands
-// (otherwise the per-phase staging kernel).
-constexpr bool kMixDwGemm = true;
 
 // The (phase, tap) pairs of each residue class of an axis's extended index,
 // for the channel-mixing input gradient: e = q u + r is read by tap t of
@@ -212,13 +209,12 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
   bytes += align256(sizeof(int) * (size_t)w * (3 + a->cmax_w));
   *off_p = bytes;
   if (plan->method == FCFS_LEARNED_MIX4) {
-    // input gradient: 32 channels per workgroup; weight gradient: partial
-    // sums of up to 8 chunks of cell rows
-    a->mix_cblocks = (int)((c + 31) / 32);
-    a->mix_otiles = (int)((a->Cout + 31) / 32);
-    a->mix_ctiles = (int)((c + 7) / 8);
+    // no adjoint tables: the workspace is [weight-gradient partials][input
+    // gradient's buffers][weight gradient's buffers]
+    bytes = 0;
+    *off_w = 0;
+    *off_p = 0;
     const int64_t rows = n * (int64_t)a->Mh;
-    a->mix_kchunks = (int)std::max<int64_t>(1, std::min<int64_t>(8, rows));
     const AxisTable &th = plan->ah, &tw = plan->aw;
     a->mix_opad = (int)((c_out + 31) / 32 * 32);
     a->mix_cpad = (int)((c + 63) / 64 * 64);
@@ -236,13 +232,14 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     const int64_t dyw_elems = n * (int64_t)ho * tw.p * a->mix_ncb * 32 * a->mix_dwopad;
     const int64_t xa_elems = n * erows * a->mix_ns * a->mix_ncb * 32 * a->mix_cpad;
     const int64_t ncb32 = (int64_t)a->mix_ncb * 32;
-    a->mix_dw_gemm = kMixDwGemm && need_dw && per_chunk * a->mix_wchunks < (1LL << 31) &&
-                     n * ho * ((ncb32 + a->mix_dwcells - 1) / a->mix_dwcells) * (a->mix_dwopad / 64) < (1LL << 31) &&
-                     n * erows * ((ncb32 + a->mix_dwxcells - 1) / a->mix_dwxcells) * (a->mix_cpad / 64) < (1LL << 31) &&
-                     (int64_t)th.p * tw.p * 16 * c_out * c < (1LL << 31);
-    if (need_dw)
-      bytes += align256(sizeof(float) * (size_t)(a->mix_dw_gemm ? a->mix_wchunks : a->mix_kchunks) * th.p * tw.p *
-                        a->Cout * c * 16);
+    // every grid within 2^31 workgroups
+    const int64_t lim = 1LL << 31;
+    if (need_dw && (per_chunk * a->mix_wchunks >= lim ||
+                    n * ho * ((ncb32 + a->mix_dwcells - 1) / a->mix_dwcells) * (a->mix_dwopad / 64) >= lim ||
+                    n * erows * ((ncb32 + a->mix_dwxcells - 1) / a->mix_dwxcells) * (a->mix_cpad / 64) >= lim ||
+                    ((int64_t)th.p * tw.p * 16 * c_out * c + 255) / 256 >= lim))
+      return FCFS_E_UNSUPPORTED;
+    if (need_dw) bytes += align256(sizeof(float) * (size_t)a->mix_wchunks * th.p * tw.p * a->Cout * c * 16);
     // input gradient on MFMA: channel-last dy, packed weights and the edge
     // buffer (the offsets follow the partial sums)
     int dhmin, dhmax, dwmin, dwmax;
@@ -298,18 +295,19 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     const int64_t gemm_blocks = n * (int64_t)a->mix_rows * a->mix_vgroups * (a->mix_cpad / 64);
     const int64_t edge_blocks = (n * c * a->mix_edge_per + 255) / 256;
     const int64_t dyc_row = dcells * tw.p * a->mix_opad;
-    a->mix_dx_gemm = gemm_blocks < (1LL << 31) && edge_blocks < (1LL << 31) && dyc_row < (1LL << 30) &&
-                     (int64_t)th.p * tw.p * 16 * a->mix_cpad * a->mix_opad < (1LL << 31);
-    if (a->mix_dx_gemm) {
-      a->mix_ws_dyc = bytes;
-      bytes += align256(sizeof(uint16_t) * (size_t)n * ho * dyc_row);
-      a->mix_ws_wpk = bytes;
-      bytes += align256(sizeof(uint16_t) * (size_t)th.p * tw.p * 16 * a->mix_cpad * a->mix_opad);
-      a->mix_ws_edge = bytes;
-      if (plan->pad != FCFS_PAD_ZERO)
-        bytes += align256(sizeof(float) * (size_t)n * c * (a->mix_edge_c + (int64_t)a->mix_rows * a->mix_cc));
-    }
-    if (a->mix_dw_gemm) {
+    const int64_t cl_blocks = n * ho * ((dcells + a->mix_clcells - 1) / a->mix_clcells);
+    const int64_t wpk_elems = (int64_t)th.p * tw.p * 16 * a->mix_cpad * a->mix_opad;
+    if (gemm_blocks >= lim || edge_blocks >= lim || cl_blocks >= lim || (wpk_elems + 255) / 256 >= lim ||
+        dcells * kMaxFactor * 32 >= lim)
+      return FCFS_E_UNSUPPORTED;
+    a->mix_ws_dyc = bytes;
+    bytes += align256(sizeof(uint16_t) * (size_t)n * ho * dyc_row);
+    a->mix_ws_wpk = bytes;
+    bytes += align256(sizeof(uint16_t) * (size_t)wpk_elems);
+    a->mix_ws_edge = bytes;
+    if (plan->pad != FCFS_PAD_ZERO)
+      bytes += align256(sizeof(float) * (size_t)n * c * (a->mix_edge_c + (int64_t)a->mix_rows * a->mix_cc));
+    if (need_dw) {
       a->mix_ws_dyw = bytes;
       bytes += align256(sizeof(uint16_t) * (size_t)dyw_elems);
       a->mix_ws_xa = bytes;
@@ -819,12 +817,12 @@ fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t
   if (mix) {
     a.weight = nullptr;
     a.mix_weight = weight;
-    if (dx && a.mix_dx_gemm) {
+    if (dx) {
       a.mix_dyc = reinterpret_cast<uint16_t*>(ws + a.mix_ws_dyc);
       a.mix_wpk = reinterpret_cast<uint16_t*>(ws + a.mix_ws_wpk);
       a.mix_edge = plan->pad != FCFS_PAD_ZERO ? reinterpret_cast<float*>(ws + a.mix_ws_edge) : nullptr;
     }
-    if (dw && a.mix_dw_gemm) {
+    if (dw) {
       a.mix_dyw = reinterpret_cast<uint16_t*>(ws + a.mix_ws_dyw);
       a.mix_xa = reinterpret_cast<uint16_t*>(ws + a.mix_ws_xa);
     }

@@ -100,8 +100,6 @@ struct BwdArgs {
   int planes_n;            // batch
   int Cout;                // output channels (C = input channels)
   const void* mix_weight;  // [p_h][p_w][Cout][C][4][4], 16-bit storage
-  int mix_cblocks;         // input-gradient workgroups per row block: ceil(C / 32)
-  int mix_otiles, mix_ctiles, mix_kchunks;   // weight gradient: 32 outputs x 8 channels x chunks of cell rows
   // input gradient on MFMA (workspace): channel-last dy with zero margin
   // cells, packed weights, and the edge buffer of the pad adjoint
   uint16_t* mix_dyc;       // [n][ho][p_w][opad / 32][dcells][32]: dy[o][ho][p_w mw + jw] at cell dleft + mw
@@ -119,7 +117,6 @@ struct BwdArgs {
   int mix_rr, mix_cc;                       // edge buffer: zone rows (part R), zone columns (part C)
   int64_t mix_edge_c;                       // floats of part R (part C follows)
   int64_t mix_edge_per;                     // input samples per plane in a fold zone
-  int mix_dx_gemm;                          // the grids fit: the input gradient on MFMA
   size_t mix_ws_dyc, mix_ws_wpk, mix_ws_edge;   // workspace offsets of the three buffers
   // weight gradient on MFMA (workspace): dy by phase and x by tap column
   // offset, 8 cells per 16-byte group; partial sums [chunk][ph][tap][o][c]
@@ -129,7 +126,6 @@ struct BwdArgs {
   int mix_s0, mix_ns;             // tap column offsets s0 .. s0 + ns - 1
   int mix_dwcells, mix_dwxcells;  // cells per block of the dy and x passes
   int mix_wchunks;                // chunks of cell rows
-  int mix_dw_gemm;                // the weight gradient on MFMA
   size_t mix_ws_dyw, mix_ws_xa;
   // (tap, d) of each residue r of the height / width axis: entries
   // [start[r], start[r + 1]), each phase | tap << 5 | (d + 64) << 7, where
