@@ -121,3 +121,51 @@ def test_mix4_input_gradient_16x64x512_sampled():
         rr, SS = r[:, :, ra:rb, ca:cb], S[:, :, ra:rb, ca:cb]
         bad = np.abs(g - rr) > UNIT["bf16"] * np.abs(rr) + UNIT_ABS["bf16"] + 1e-5 * SS + 1e-30
         assert not bad.any(), (n, R0, C0, int(bad.sum()))
+
+
+def test_mix4_weight_gradient_16x64x512_windows():
+    """The weight gradient of the 16x64x512^2 layer at 5/4 (BF16, 64 -> 64)
+    through the full-size launch (every chunk of cell rows and the chunk
+    reduction), with dy zero outside three windows of 8 x 8 cells: the top
+    left corner of image 0 and the bottom right corner of image 15 (where the
+    reflect padding supplies taps) and an interior window of image 7. By
+    linearity the result is the sum of the windows' weight gradients, each
+    from the oracle's adjoint on a crop that holds every tap of its cells."""
+    import torch
+    import paper_2203_10670_amd as fc
+    N, C, H, W, p, q = 16, 64, 512, 512, 5, 4
+    Mh = Mw = 128
+    x = storage_round(synth.normal(4, (N, C, H, W)), "bf16")
+    w = storage_round(synth.normal(5, (p, p, C, C, 4, 4), std=1 / 32), "bf16")
+    win = [(0, (0, 8), (0, 8)), (15, (Mh - 8, Mh), (Mw - 8, Mw)), (7, (60, 68), (33, 41))]
+    dy = np.zeros((N, C, p * Mh, p * Mw), dtype=np.float32)
+    for k, (n, (a0, a1), (b0, b1)) in enumerate(win):
+        vals = storage_round(synth.normal(20 + k, (C, p * (a1 - a0), p * (b1 - b0))), "bf16")
+        dy[n, :, p * a0: p * a1, p * b0: p * b1] = vals
+    pl = fc.Plan(p, q, "mix4", "reflect")
+    _, gdw = pl.backward(torch.from_numpy(dy).cuda().to(torch.bfloat16), (N, C, H, W),
+                         x=torch.from_numpy(x).cuda().to(torch.bfloat16),
+                         weight=torch.from_numpy(w).cuda().to(torch.bfloat16).contiguous(), need_dw=True)
+    torch.cuda.synchronize()
+    gdw = gdw.cpu().numpy()
+    _say("mix4 dw 16x64x512 windows done")
+    rdw = np.zeros(w.shape, dtype=np.float64)
+    sdw = np.zeros(w.shape, dtype=np.float64)
+    for n, (a0, a1), (b0, b1) in win:
+        # crop at multiples of q with two cells of margin (every tap of the
+        # window's cells inside it; cut edges far from them)
+        r0, r1 = max(0, q * (a0 - 2)), min(H, q * (a1 + 2))
+        c0, c1 = max(0, q * (b0 - 2)), min(W, q * (b1 + 2))
+        xc = x[n:n + 1, :, r0:r1, c0:c1]
+        shape = xc.shape
+        hc, wc = -(-(r1 - r0) // q), -(-(c1 - c0) // q)
+        dyc = np.zeros((1, C, p * hc, p * wc), dtype=np.float64)
+        ka, kb = a0 - r0 // q, b0 - c0 // q
+        dyc[0, :, p * ka: p * (ka + a1 - a0), p * kb: p * (kb + b1 - b0)] = dy[n, :, p * a0: p * a1, p * b0: p * b1]
+        _, r = oracle.backward(dyc, shape, p, q, "mix4", "reflect", x=xc, weight=w, need_dx=False, need_dw=True)
+        _, sc = oracle.condition_backward(dyc, shape, p, q, "mix4", "reflect", x=xc, weight=w, need_dw=True)
+        rdw += r
+        sdw += sc
+    bad = np.abs(gdw - rdw) > 1e-5 * sdw + 1e-30
+    assert not bad.any(), "dw: %d bad of %d, first %s gpu %r oracle %r" % (
+        int(bad.sum()), bad.size, np.argwhere(bad)[0], gdw[tuple(np.argwhere(bad)[0])], rdw[tuple(np.argwhere(bad)[0])])
