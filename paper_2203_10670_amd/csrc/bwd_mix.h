@@ -164,7 +164,8 @@ __device__ __forceinline__ int64_t edge_index(const BwdArgs& a, int64_t pc, int 
 }
 
 // One extended row, kw chunks of 16 MTN consecutive v, 64 channels, every
-// width class.
+// width class. Each wave keeps two steps of fragments in flight (one for
+// MTN = 4).
 template <int DT, int MTN>
 __global__ __launch_bounds__(kThreads, 3) void dx_mix_gemm_kernel(const BwdArgs a) {
   using M = Mfma<DT>;
@@ -227,30 +228,55 @@ __global__ __launch_bounds__(kThreads, 3) void dx_mix_gemm_kernel(const BwdArgs 
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // steps (height entry hi, width entry wi, 32 outputs os)
+    // steps (height entry hi, width entry wi, 32 outputs os). The fragment
+    // addresses are linear in the three: running pointers, with the height
+    // entry's row bases set when hi changes and the width entry's offsets
+    // when wi changes (few scalar instructions per step).
     const int steps = hcount * (we - ws) * nst;
+    const int64_t osA = (int64_t)a.mix_dcells * kDxgO, osB = (int64_t)4 * a.mix_cpad * 8;
     int hi = hfirst, wi = ws, os = 0;
+    const uint16_t *rA = nullptr, *rB = nullptr, *pA = nullptr, *pB = nullptr;
+    auto set_h = [&]() {
+      const int e = a.mix_hl[hi];
+      const int jh = e & 31, ta = (e >> 5) & 3, mh = uh - ((e >> 7) - 64);
+      rA = dycn + (int64_t)(TH.p * mh + jh) * drow;
+      rB = a.mix_wpk + (int64_t)(jh * TW.p * 16 + ta * 4) * nst * osB;
+    };
+    auto set_w = [&]() {
+      const int e = a.mix_wl[wi];
+      const int jw = e & 31, tb = (e >> 5) & 3, dw = (e >> 7) - 64;
+      pA = rA + ((int64_t)jw * nst * a.mix_dcells - dw) * kDxgO;
+      pB = rB + (int64_t)(jw * 16 + tb) * nst * osB;
+    };
+    if (steps > 0) {
+      set_h();
+      set_w();
+    }
     auto advance = [&]() {
-      if (++os < nst) return;
+      if (++os < nst) {
+        pA += osA;
+        pB += osB;
+        return;
+      }
       os = 0;
-      if (++wi < we) return;
+      if (++wi < we) {
+        set_w();
+        return;
+      }
       wi = ws;
       do ++hi;
       while (hi < he && !h_ok(hi));
+      if (hi < he) {
+        set_h();
+        set_w();
+      }
     };
-    u16x8 af0[MTN], bf0[4], af1[MTN], bf1[4];
+    u16x8 af0[MTN], bf0[4], af1[MTN], bf1[4], af2[MTN], bf2[4];
     auto load = [&](u16x8 (&A)[MTN], u16x8 (&B)[4]) __attribute__((always_inline)) {
-      const int he_ = a.mix_hl[hi], we_ = a.mix_wl[wi];
-      const int jh = he_ & 31, ta = (he_ >> 5) & 3, mh = uh - ((he_ >> 7) - 64);
-      const int jw = we_ & 31, tb = (we_ >> 5) & 3, dw = (we_ >> 7) - 64;
-      const uint16_t* const ab =
-          dycn + (int64_t)(TH.p * mh + jh) * drow + ((int64_t)(jw * nst + os) * a.mix_dcells - dw) * kDxgO;
-      const uint16_t* const bb =
-          a.mix_wpk + ((((int64_t)jh * TW.p + jw) * 16 + ta * 4 + tb) * nst + os) * 4 * a.mix_cpad * 8;
 #pragma unroll
-      for (int mt = 0; mt < MTN; ++mt) A[mt] = *reinterpret_cast<const u16x8*>(ab + aoff[mt]);
+      for (int mt = 0; mt < MTN; ++mt) A[mt] = *reinterpret_cast<const u16x8*>(pA + aoff[mt]);
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) B[nt] = *reinterpret_cast<const u16x8*>(bb + boff + 16 * 8 * nt);
+      for (int nt = 0; nt < 4; ++nt) B[nt] = *reinterpret_cast<const u16x8*>(pB + boff + 16 * 8 * nt);
       advance();
     };
     auto mma = [&](const u16x8 (&A)[MTN], const u16x8 (&B)[4]) __attribute__((always_inline)) {
@@ -259,15 +285,32 @@ __global__ __launch_bounds__(kThreads, 3) void dx_mix_gemm_kernel(const BwdArgs 
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = M::mma(A[mt], B[nt], acc[mt][nt]);
     };
-    // two register buffers: step s + 1's fragments load during step s's MFMAs
-    if (steps > 0) load(af0, bf0);
-    for (int s = 0; s + 1 < steps; s += 2) {
-      load(af1, bf1);                      // step s + 1
-      mma(af0, bf0);                       // step s
-      if (s + 2 < steps) load(af0, bf0);   // step s + 2
-      mma(af1, bf1);                       // step s + 1
+    if constexpr (MTN <= 3) {
+      // three register buffers: steps s + 1 and s + 2 load during step s's MFMAs
+      if (steps > 0) load(af0, bf0);
+      if (steps > 1) load(af1, bf1);
+      int s = 0;
+      for (; s + 2 < steps; s += 3) {
+        load(af2, bf2);                      // step s + 2
+        mma(af0, bf0);                       // step s
+        if (s + 3 < steps) load(af0, bf0);   // step s + 3
+        mma(af1, bf1);                       // step s + 1
+        if (s + 4 < steps) load(af1, bf1);   // step s + 4
+        mma(af2, bf2);                       // step s + 2
+      }
+      if (s < steps) mma(af0, bf0);          // the last one or two steps
+      if (s + 1 < steps) mma(af1, bf1);
+    } else {
+      // two buffers (the registers of a third would spill)
+      if (steps > 0) load(af0, bf0);
+      for (int s = 0; s + 1 < steps; s += 2) {
+        load(af1, bf1);                      // step s + 1
+        mma(af0, bf0);                       // step s
+        if (s + 2 < steps) load(af0, bf0);   // step s + 2
+        mma(af1, bf1);                       // step s + 1
+      }
+      if (steps & 1) mma(af0, bf0);          // the last step
     }
-    if (steps & 1) mma(af0, bf0);          // the last step
 
     // slot epilogue: lane (c = c0 + 16 nt + li) holds v = vb + 16 mt + 4 g4 + i.
     // Fold-zone and margin positions go to the edge buffer; the others are
