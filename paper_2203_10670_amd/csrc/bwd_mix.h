@@ -361,23 +361,23 @@ __global__ __launch_bounds__(kThreads, 3) void dx_mix_gemm_kernel(const BwdArgs 
 template <int DT>
 __global__ __launch_bounds__(kThreads) void dx_mix_edge_kernel(const BwdArgs a) {
   using S = Store<DT>;
-  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (g >= (int64_t)a.planes_n * a.C * a.mix_edge_per) return;
-  const int64_t pc = g / a.mix_edge_per;
-  int64_t t = g - pc * a.mix_edge_per;
+  // blocks (x: 256 zone samples of a plane, y: planes, striding past 65535)
+  int t = (int)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= a.mix_edge_per) return;
   int i, j;
   const int zr = a.mix_top + a.mix_bot;
-  if (t < (int64_t)zr * a.W) {
-    const int k = (int)(t / a.W);
-    j = (int)(t - (int64_t)k * a.W);
+  if (t < zr * a.W) {
+    const int k = t / a.W;
+    j = t - k * a.W;
     i = k < a.mix_top ? k : a.H - a.mix_bot + (k - a.mix_top);
   } else {
-    t -= (int64_t)zr * a.W;
+    t -= zr * a.W;
     const int zc = a.mix_cl + a.mix_cr;
-    const int k = (int)(t / zc), m = (int)(t - (int64_t)k * zc);
+    const int k = t / zc, m = t - k * zc;
     i = a.mix_top + k;
     j = m < a.mix_cl ? m : a.W - a.mix_cr + (m - a.mix_cl);
   }
+  for (int64_t pc = blockIdx.y; pc < (int64_t)a.planes_n * a.C; pc += gridDim.y) {
   float s = 0.f;
   auto add_row = [&](int eh) {
     for (int ew = a.mix_ew0; ew < 0; ++ew)
@@ -392,6 +392,7 @@ __global__ __launch_bounds__(kThreads) void dx_mix_edge_kernel(const BwdArgs a) 
   for (int eh = a.H; eh <= a.mix_eh1; ++eh)
     if (pad_source(eh, a.H, a.pad) == i) add_row(eh);
   S::store(reinterpret_cast<typename S::T*>(a.dx) + (pc * a.H + i) * a.W + j, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -602,20 +603,22 @@ __global__ __launch_bounds__(kThreads, 2) void dw_mix_gemm_kernel(const BwdArgs 
 
   const int steps = (g_hi - g_lo) * ncb;
   int g = g_lo, cb = 0;
-  const uint16_t *yrow = nullptr, *xrow = nullptr;
+  // running pointers to the step's 32-cell blocks, set at each cell row
+  const uint16_t *pa = nullptr, *pb = nullptr;
   auto set_row = [&]() {
     const int n = g / a.Mh, mh = g - n * a.Mh;
     const int ho = TH.p * mh + jh, er = TH.q * mh + TH.off[jh] + ta - a.mix_eh0;
-    yrow = a.mix_dyw + (((int64_t)n * a.Ho + ho) * TW.p + jw) * ncb * ystride;
-    xrow = a.mix_xa + (((int64_t)n * erows + er) * a.mix_ns + s) * ncb * xstride;
+    pa = a.mix_dyw + (((int64_t)n * a.Ho + ho) * TW.p + jw) * ncb * ystride;
+    pb = a.mix_xa + (((int64_t)n * erows + er) * a.mix_ns + s) * ncb * xstride;
   };
   if (steps > 0) set_row();
   u16x8 ast, bf0[4], bf1[4];
   auto gload = [&](u16x8 (&B)[4]) __attribute__((always_inline)) {
-    ast = *reinterpret_cast<const u16x8*>(yrow + cb * ystride + aoff);
-    const uint16_t* const bb = xrow + cb * xstride;
+    ast = *reinterpret_cast<const u16x8*>(pa + aoff);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) B[nt] = *reinterpret_cast<const u16x8*>(bb + boff + 16 * 8 * nt);
+    for (int nt = 0; nt < 4; ++nt) B[nt] = *reinterpret_cast<const u16x8*>(pb + boff + 16 * 8 * nt);
+    pa += ystride;
+    pb += xstride;
     if (++cb == ncb) {
       cb = 0;
       if (++g < g_hi) set_row();
@@ -701,8 +704,11 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
       default: hipLaunchKernelGGL((dx_mix_gemm_kernel<DT, 4>), ggrid, block, glds, stream, a); break;
     }
     if (a.mix_edge) {
-      const int64_t eblocks = ((int64_t)a.planes_n * a.C * a.mix_edge_per + kThreads - 1) / kThreads;
-      if (eblocks > 0) hipLaunchKernelGGL((dx_mix_edge_kernel<DT>), dim3((unsigned)eblocks), block, 0, stream, a);
+      const int64_t eblocks = (a.mix_edge_per + kThreads - 1) / kThreads;
+      const int64_t planes = (int64_t)a.planes_n * a.C;
+      if (eblocks > 0)
+        hipLaunchKernelGGL((dx_mix_edge_kernel<DT>), dim3((unsigned)eblocks, (unsigned)std::min<int64_t>(planes, 65535)),
+                           block, 0, stream, a);
     }
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }

@@ -224,8 +224,8 @@ inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... arg
   std::unique_ptr<std::barrier<>> block_bar;
   std::barrier<> start((std::ptrdiff_t)nthreads + 1), done((std::ptrdiff_t)nthreads + 1);
   std::vector<hostemu::WaveScratch> scratch(nwaves);
-  unsigned cur = 0;
-  auto prepare = [&](unsigned b) {
+  unsigned long long cur = 0;
+  auto prepare = [&](unsigned long long b) {
     bars.clear();
     for (unsigned w = 0; w < nwaves; ++w)
       bars.emplace_back(new std::barrier<>((std::ptrdiff_t)std::min(64u, nthreads - 64 * w)));
@@ -234,13 +234,15 @@ inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... arg
       std::memset(hostemu::lds_arrays[i], 0xff, lds);
     cur = b;
   };
+  // workgroups in x-fastest order over the whole (x, y, z) grid
+  const unsigned long long nblocks = (unsigned long long)grid.x * grid.y * grid.z;
   std::vector<std::thread> th;
   for (unsigned t = 0; t < nthreads; ++t)
     th.emplace_back([&, t] {
-      for (unsigned b = 0; b < grid.x; ++b) {
+      for (unsigned long long b = 0; b < nblocks; ++b) {
         start.arrive_and_wait();
-        hostemu::tid_ = dim3(t);
-        hostemu::bid_ = dim3(cur);
+        hostemu::tid_ = dim3(t, 0, 0);
+        hostemu::bid_ = dim3(cur % grid.x, (cur / grid.x) % grid.y, cur / ((unsigned long long)grid.x * grid.y));
         hostemu::grid_ = grid;
         hostemu::wave_bar_ = bars[t / 64].get();
         hostemu::block_bar_ = block_bar.get();
@@ -251,7 +253,7 @@ inline void hostemu_launch(K kernel, dim3 grid, dim3 block, size_t lds, A... arg
         done.arrive_and_wait();
       }
     });
-  for (unsigned b = 0; b < grid.x; ++b) {
+  for (unsigned long long b = 0; b < nblocks; ++b) {
     prepare(b);
     start.arrive_and_wait();
     done.arrive_and_wait();
