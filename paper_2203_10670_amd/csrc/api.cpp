@@ -224,8 +224,8 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     a->mix_ncb = (a->Mw + 31) / 32;
     a->mix_s0 = tw.omin;
     a->mix_ns = tw.omax - tw.omin + 1;
-    a->mix_dwcells = std::max(8, std::min(32, (256 / tw.p) / 8 * 8));
-    a->mix_dwxcells = tw.q <= 8 ? 32 : 8;
+    a->mix_dwcells = std::max(8, std::min(64, (256 / tw.p) / 8 * 8));
+    a->mix_dwxcells = tw.q <= 4 ? 64 : (tw.q <= 8 ? 32 : 8);
     const int64_t per_chunk = (int64_t)th.p * tw.p * 4 * (a->mix_dwopad / 64) * (a->mix_cpad / 64);
     a->mix_wchunks = (int)std::max<int64_t>(1, std::min<int64_t>(rows, (2048 + per_chunk - 1) / per_chunk));
     const int64_t erows = (int64_t)th.q * (a->Mh - 1) + th.omax - th.omin + 1;
