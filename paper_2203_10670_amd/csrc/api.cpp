@@ -270,7 +270,7 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     const int64_t dright = std::max<int64_t>(0, vend - 1 - dwmin - (a->Mw - 1));
     const int64_t dcells = a->mix_dleft + a->Mw + dright;
     a->mix_dcells = (int)std::min<int64_t>(dcells, 1 << 30);
-    a->mix_clcells = std::max(1, 128 / tw.p);
+    a->mix_clcells = std::max(1, kDxcColumns / tw.p);
     // fold zones of replicate / reflect: the samples the margins copy (every
     // sample of an axis short enough for a reflection to wrap)
     auto zone = [&](int len, int e0, int e1, int* lo, int* hi) {

@@ -61,14 +61,14 @@ constexpr int kThreads = 256;
 constexpr int kDxgO = 32;    // outputs per MFMA K-step
 constexpr int kDxgC = 64;    // channels per workgroup (4 N tiles)
 
-// dyc from dy[n][o][ho][wo]: a block takes kw cells (all p_w phases, at most
-// 128 columns col = cell * p_w + jw, wo = col - dleft * p_w; zeros outside
+// dyc from dy[n][o][ho][wo]: a block takes mix_clcells cells (all p_w phases, at most
+// 256 columns col = cell * p_w + jw, wo = col - dleft * p_w; zeros outside
 // the row) of one output row, 64 outputs at a time through an LDS tile
 // [column][output]. With W_out even a lane reads an aligned column pair of 8
 // outputs (8 dword loads, coalesced over pairs) and writes two 16-byte
 // column chunks; then each lane moves 16-byte chunks of 8 outputs, ordered
 // so that consecutive lanes write consecutive bytes of dyc.
-constexpr int kDxcPitch = 72;   // LDS tile pitch (16-bit units): [128 columns][64 outputs + 8]
+constexpr int kDxcPitch = 72;   // LDS tile pitch (16-bit units): [kDxcColumns columns][64 outputs + 8]
 __global__ __launch_bounds__(kThreads) void dx_mix_channel_last_kernel(const BwdArgs a) {
   extern __shared__ float smem[];
   uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
@@ -690,7 +690,7 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
     // zones to the edge buffer), then the fold zones
     const int64_t cl_blocks = (int64_t)a.planes_n * a.Ho * ((a.mix_dcells + a.mix_clcells - 1) / a.mix_clcells);
     hipLaunchKernelGGL(dx_mix_channel_last_kernel, dim3((unsigned)cl_blocks), block,
-                       sizeof(uint16_t) * 128 * kDxcPitch, stream, a);
+                       sizeof(uint16_t) * kDxcColumns * kDxcPitch, stream, a);
     const int64_t wtotal = (int64_t)a.th.p * a.tw_tab.p * 16 * a.mix_cpad * a.mix_opad;
     hipLaunchKernelGGL(dx_mix_pack_weights_kernel, dim3((unsigned)((wtotal + kThreads - 1) / kThreads)), block, 0,
                        stream, a);

@@ -107,7 +107,7 @@ struct BwdArgs {
   float* mix_edge;         // z at the positions the pad adjoint folds (null for zero padding)
   int mix_opad, mix_cpad;  // C_out rounded up to 32, C_in rounded up to 64
   int mix_dleft, mix_dcells;                // margin cells left of cell 0; cells per phase row
-  int mix_clcells;                          // cells per block of the channel-last pass (<= 128 columns)
+  int mix_clcells;                          // cells per block of the channel-last pass (<= kDxcColumns columns)
   int mix_eh0, mix_eh1, mix_ew0, mix_ew1;   // extended positions the taps read (inclusive)
   int mix_r0, mix_rows;                     // extended rows of the GEMM: [r0, r0 + rows)
   int mix_v0, mix_vw, mix_mtn, mix_vchunks; // width-class positions [v0, v0 + vw) in chunks of 16 mtn
@@ -136,6 +136,7 @@ struct BwdArgs {
 };
 
 constexpr int kMixOut = 32;   // output channels per channel-mixing workgroup
+constexpr int kDxcColumns = 256;   // dy columns per block of the input gradient's layout pass
 
 struct MixArgs {
   const void* x;         // [N][Cin][H][W], 16-bit storage
