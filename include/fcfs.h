@@ -187,7 +187,11 @@ fcfs_status fcfs_forward_config(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, i
                                 int64_t h, int64_t w, int* kernel_id, int* strip_width,
                                 int* band_cells, int64_t* waves);
 
-/* Device workspace bytes fcfs_backward needs for these sizes (0 if none). */
+/* Device workspace bytes fcfs_backward needs for these sizes (0 if none),
+ * with the weight gradient for learned methods. For LEARNED_MIX4 the
+ * workspace holds re-laid-out copies of dy (two layouts), of the padded x (one
+ * per tap column offset) and the weights, and the weight gradient's partial
+ * sums: about 3.1 GB for 16x64x512^2 at 5/4. */
 fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in,
                                     int64_t h, int64_t w, int64_t c_out, size_t* bytes);
 
@@ -209,15 +213,16 @@ fcfs_status fcfs_backward_workspace(fcfs_plan_t plan, fcfs_dtype dtype, int64_t 
  *   workspace / ws_bytes: device scratch of at least fcfs_backward_workspace
  *        bytes (NULL allowed when that is 0).
  * Errors: as fcfs_forward, plus FCFS_E_INVAL for a workspace that is too small,
- * and FCFS_E_UNSUPPORTED for an output axis of 2^24 samples or more. */
+ * and FCFS_E_UNSUPPORTED for an output axis of 2^24 samples or more, or (for
+ * LEARNED_MIX4) sizes whose launches would pass 2^31 workgroups. */
 fcfs_status fcfs_backward(fcfs_plan_t plan, fcfs_dtype dtype, int64_t n, int64_t c_in, int64_t h,
                           int64_t w, const void* x, const void* weight, int64_t c_out,
                           const void* dy, void* dx, float* dw, void* workspace, size_t ws_bytes,
                           hipStream_t stream);
 
 /* Largest workspace fcfs_backward_noalloc can serve: 64 MiB (the 8x64x256^2
- * learned depthwise backward at 3/4 needs about 4.7 MB, the 16x64x512^2
- * channel-mixing backward at 5/4 about 52 MB). */
+ * learned depthwise backward at 3/4 needs about 4.7 MB; the 16x64x512^2
+ * channel-mixing backward at 5/4 needs about 3.1 GB and is refused). */
 #define FCFS_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 /* fcfs_backward for callers that cannot allocate device memory (code under
