@@ -420,6 +420,9 @@ constexpr int kDwyPitch = 258;   // LDS pitch (16-bit units) of the dy pass tile
 // w reads rows w, w + 4, ... of the tile (aligned column pairs when W_out is
 // even), then lane o gathers 8 cells of one phase from its row (the pitch
 // puts the 64 rows on distinct banks) and writes them as 16 bytes.
+// DYC: also the input gradient's layout of the same cells (dyc, margins
+// aside), so that a call with both gradients reads dy once.
+template <bool DYC>
 __global__ __launch_bounds__(kThreads) void dw_mix_dy_kernel(const BwdArgs a) {
   extern __shared__ float smem[];
   uint16_t* const tile = reinterpret_cast<uint16_t*>(smem);
@@ -490,6 +493,41 @@ __global__ __launch_bounds__(kThreads) void dw_mix_dy_kernel(const BwdArgs a) {
     for (int i = 0; i < 8; ++i) v[i] = tile[lane * kDwyPitch + pw * (8 * gb + i) + jw];
     *reinterpret_cast<u16x8*>(orow + ((((int64_t)jw * a.mix_ncb + mw / 32) * 4 + (mw % 32) / 8) * a.mix_dwopad + o0 + lane) * 8) = v;
   }
+  if constexpr (DYC) {
+    // chunks (jw, 32 outputs sl, cell, 8 outputs g), g fastest: dyc[..][jw][os][dleft + mw][32]
+    const int nst = a.mix_opad / kDxgO;
+    const int cells = min(bc, a.Mw - mw0);
+    uint16_t* const crow = a.mix_dyc + ((int64_t)n * a.Ho + ho) * pw * nst * a.mix_dcells * kDxgO;
+    for (int e = threadIdx.x; e < pw * 2 * bc * 4; e += kThreads) {
+      const int g = e & 3, cell = (e >> 2) % bc, sj = (e >> 2) / bc;
+      const int sl = sj & 1, jw = sj >> 1;
+      const int os = o0 / kDxgO + sl;
+      if (cell >= cells || os >= nst) continue;
+      u16x8 v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = tile[(sl * kDxgO + 8 * g + i) * kDwyPitch + pw * cell + jw];
+      *reinterpret_cast<u16x8*>(crow + (((int64_t)jw * nst + os) * a.mix_dcells + a.mix_dleft + mw0 + cell) * kDxgO + 8 * g) = v;
+    }
+  }
+}
+
+// Zeros in dyc's margin cells (before cell 0 and from cell M_w on), which the
+// fused layout pass leaves: chunks (n, ho, jw, os, margin cell, 8 outputs).
+__global__ __launch_bounds__(kThreads) void dx_mix_dyc_margin_kernel(const BwdArgs a) {
+  const int nst = a.mix_opad / kDxgO;
+  const int margin = a.mix_dcells - a.Mw;   // dleft + right margin
+  const int64_t per_row = (int64_t)a.tw_tab.p * nst * margin * 4;
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= (int64_t)a.planes_n * a.Ho * per_row) return;
+  const int64_t row = e / per_row;   // n * Ho + ho
+  int64_t r = e - row * per_row;
+  const int g = (int)(r % 4); r /= 4;
+  const int m = (int)(r % margin); r /= margin;
+  const int os = (int)(r % nst);
+  const int jw = (int)(r / nst);
+  const int cell = m < a.mix_dleft ? m : a.Mw + m;   // dyc cell index
+  *reinterpret_cast<u16x8*>(a.mix_dyc + ((row * a.tw_tab.p + jw) * nst + os) * (int64_t)a.mix_dcells * kDxgO +
+                            (int64_t)cell * kDxgO + 8 * g) = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
 }
 
 // xa from x: a block takes 64 channels of one extended row and dwxcells
@@ -685,12 +723,24 @@ __global__ __launch_bounds__(kThreads) void dw_mix_gemm_reduce_kernel(const BwdA
 template <int DT>
 fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
   const dim3 block(kThreads);
-  if (a.dx) {
-    // dy by width phase, packed weights, z on MFMA (dx directly, the fold
-    // zones to the edge buffer), then the fold zones
+  const int64_t ncb32 = (int64_t)a.mix_ncb * 32;
+  const int64_t yblocks = (int64_t)a.planes_n * a.Ho * ((ncb32 + a.mix_dwcells - 1) / a.mix_dwcells) * (a.mix_dwopad / 64);
+  if (a.dx && a.dw) {
+    // both gradients: one pass over dy writes both layouts, then dyc's margins
+    hipLaunchKernelGGL(dw_mix_dy_kernel<true>, dim3((unsigned)yblocks), block, sizeof(uint16_t) * 64 * kDwyPitch, stream, a);
+    const int64_t mchunks = (int64_t)a.planes_n * a.Ho * a.tw_tab.p * (a.mix_opad / kDxgO) * (a.mix_dcells - a.Mw) * 4;
+    if (mchunks > 0)
+      hipLaunchKernelGGL(dx_mix_dyc_margin_kernel, dim3((unsigned)((mchunks + kThreads - 1) / kThreads)), block, 0, stream, a);
+  } else if (a.dx) {
     const int64_t cl_blocks = (int64_t)a.planes_n * a.Ho * ((a.mix_dcells + a.mix_clcells - 1) / a.mix_clcells);
     hipLaunchKernelGGL(dx_mix_channel_last_kernel, dim3((unsigned)cl_blocks), block,
                        sizeof(uint16_t) * kDxcColumns * kDxcPitch, stream, a);
+  } else if (a.dw) {
+    hipLaunchKernelGGL(dw_mix_dy_kernel<false>, dim3((unsigned)yblocks), block, sizeof(uint16_t) * 64 * kDwyPitch, stream, a);
+  }
+  if (a.dx) {
+    // packed weights, z on MFMA (dx directly, the fold zones to the edge
+    // buffer), then the fold zones
     const int64_t wtotal = (int64_t)a.th.p * a.tw_tab.p * 16 * a.mix_cpad * a.mix_opad;
     hipLaunchKernelGGL(dx_mix_pack_weights_kernel, dim3((unsigned)((wtotal + kThreads - 1) / kThreads)), block, 0,
                        stream, a);
@@ -713,11 +763,8 @@ fcfs_status launch_backward_mix_dt(const BwdArgs& a, hipStream_t stream) {
     if (hipGetLastError() != hipSuccess) return FCFS_E_DEVICE;
   }
   if (a.dw) {
-    // dy by phase, x by tap offset, the GEMM per (phase, tap row) and chunk,
-    // then the chunks added in order
-    const int64_t ncb32 = (int64_t)a.mix_ncb * 32;
-    const int64_t yblocks = (int64_t)a.planes_n * a.Ho * ((ncb32 + a.mix_dwcells - 1) / a.mix_dwcells) * (a.mix_dwopad / 64);
-    hipLaunchKernelGGL(dw_mix_dy_kernel, dim3((unsigned)yblocks), block, sizeof(uint16_t) * 64 * kDwyPitch, stream, a);
+    // x by tap offset, the GEMM per (phase, tap row) and chunk, then the
+    // chunks added in order
     const int64_t erows = a.mix_eh1 - a.mix_eh0 + 1;
     const int64_t xblocks = (int64_t)a.planes_n * erows * ((ncb32 + a.mix_dwxcells - 1) / a.mix_dwxcells) * (a.mix_cpad / 64);
     hipLaunchKernelGGL(dw_mix_x_kernel, dim3((unsigned)xblocks), block,
