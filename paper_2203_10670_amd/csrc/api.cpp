@@ -219,7 +219,8 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     a->mix_opad = (int)((c_out + 31) / 32 * 32);
     a->mix_cpad = (int)((c + 63) / 64 * 64);
     // weight gradient on MFMA: dy by phase and x by tap offset, cells in
-    // blocks of 32; chunks of cell rows for about 2048 workgroups
+    // blocks of 32; chunks of cell rows for about 4096 workgroups (2048 and
+    // 8192 ran 3-5% slower at 16x64x512^2, 5/4)
     a->mix_dwopad = (int)((c_out + 63) / 64 * 64);
     a->mix_ncb = (a->Mw + 31) / 32;
     a->mix_s0 = tw.omin;
@@ -227,7 +228,11 @@ static fcfs_status plan_backward(const fcfs_plan_* plan, int64_t n, int64_t c, i
     a->mix_dwcells = std::max(8, std::min(64, (256 / tw.p) / 8 * 8));
     a->mix_dwxcells = tw.q <= 4 ? 64 : (tw.q <= 8 ? 32 : 8);
     const int64_t per_chunk = (int64_t)th.p * tw.p * 4 * (a->mix_dwopad / 64) * (a->mix_cpad / 64);
-    a->mix_wchunks = (int)std::max<int64_t>(1, std::min<int64_t>(rows, (2048 + per_chunk - 1) / per_chunk));
+#ifndef FCFS_MIX_DW_WORKGROUPS
+#define FCFS_MIX_DW_WORKGROUPS 4096
+#endif
+    a->mix_wchunks = (int)std::max<int64_t>(
+        1, std::min<int64_t>(rows, (FCFS_MIX_DW_WORKGROUPS + per_chunk - 1) / per_chunk));
     const int64_t erows = (int64_t)th.q * (a->Mh - 1) + th.omax - th.omin + 1;
     const int64_t dyw_elems = n * (int64_t)ho * tw.p * a->mix_ncb * 32 * a->mix_dwopad;
     const int64_t xa_elems = n * erows * a->mix_ns * a->mix_ncb * 32 * a->mix_cpad;
