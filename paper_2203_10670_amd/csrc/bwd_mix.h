@@ -47,14 +47,15 @@ constexpr int kThreads = 256;
 // [cell][o % 32]), and the weights as wpk[jh][jw][a][b][o / 32][o % 32 / 8]
 // [c][o % 8]. An A fragment (16 cells x 32 outputs) and a B fragment (32
 // outputs x 16 channels) are then each 1 KB of consecutive memory, one
-// 16-byte load per lane, and a cell outside the row reads zeros.
+// 16-byte load per lane, and a cell outside the row reads zeros. (A call
+// with both gradients gets dyc from the weight gradient's pass over dy.)
 //
 // A workgroup takes one extended row, kw chunks of 16 mtn consecutive v and
 // 64 channels, for every width class (waves take the (class, chunk) slots in
 // turn; with q_w = 4 one class each, so the four waves read the same dy
 // cells and share them in L1). A wave walks its class's (tap pair, 32
-// outputs) steps with the next step's fragments in flight during the current
-// step's MFMAs. The epilogue interleaves the classes in LDS and writes each dx
+// outputs) steps with the next two steps' fragments in flight during the
+// current step's MFMAs. The epilogue interleaves the classes in LDS and writes each dx
 // row segment contiguously, rounded once; the samples the pad adjoint folds
 // (and the margins) go to the edge buffer in FP32, and a last pass adds each
 // sample's preimages there in ascending order and rounds once.
