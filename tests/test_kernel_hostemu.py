@@ -158,6 +158,13 @@ def test_backward_learned_and_edges():
               {"mode": "bwd", "p": 3, "q": 2, "method": "bicubic", "pad": "replicate", "dtype": "bf16",
                "shape": [1, 2, 9, 40]},
               {"mode": "bwd", "p": 3, "q": 4, "method": "dw4", "pad": "zero", "dtype": "bf16", "shape": [2, 2, 16, 40]},
+              # one gradient at a time (dw alone: the one-pass kernel without
+              # its input-gradient part; dx alone: the gather kernel); rows
+              # wider than a workgroup
+              {"mode": "bwd", "p": 3, "q": 4, "method": "dw4", "pad": "reflect", "parts": "dw", "shape": [1, 2, 37, 75]},
+              {"mode": "bwd", "p": 5, "q": 4, "method": "dw4", "pad": "replicate", "parts": "dx",
+               "shape": [1, 2, 19, 50]},
+              {"mode": "bwd", "p": 2, "q": 3, "method": "dw4", "pad": "reflect", "shape": [1, 1, 26, 600]},
               {"mode": "bwd", "p": 3, "q": 2, "pw": 4, "qw": 5, "method": "bicubic", "pad": "zero",
                "shape": [1, 1, 11, 30]}]
     _run(cases)
