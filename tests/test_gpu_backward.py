@@ -84,6 +84,27 @@ def test_learned_depthwise_gradients(p, q, pad):
     check_grads(x, dy, p, q, "dw4", pad, weight=w, need_dw=True, what=f"dw4 {p}/{q} {pad}")
 
 
+@pytest.mark.parametrize("p,q,pad,dtype", [(2, 3, "reflect", "f32"), (3, 4, "replicate", "bf16")])
+def test_learned_depthwise_wide_rows_one_gradient_at_a_time(p, q, pad, dtype):
+    # rows of 600 samples (three column blocks of the input-gradient kernel);
+    # each gradient requested alone equals the oracle's, and equals the one
+    # computed beside the other bit for bit
+    from math import gcd
+    g = gcd(p, q)
+    x = storage_round(synth.normal(83, (2, 3, 23, 600)), dtype)
+    w = synth.normal(84, (3, p // g, p // g, 4, 4))
+    dy = storage_round(synth.normal(85, (2, 3, (p // g) * -(-23 // (q // g)), (p // g) * -(-600 // (q // g)))), dtype)
+    _say("dw4 wide", p, q, pad, dtype)
+    dx_only, _ = gpu_backward(x, dy, p, q, "dw4", pad, dtype, w, need_dx=True, need_dw=False)
+    _, dw_only = gpu_backward(x, dy, p, q, "dw4", pad, dtype, w, need_dx=False, need_dw=True)
+    dx_both, dw_both = gpu_backward(x, dy, p, q, "dw4", pad, dtype, w, need_dx=True, need_dw=True)
+    assert np.array_equal(dx_only, dx_both) and np.array_equal(dw_only, dw_both)
+    rdx, rdw = oracle.backward(dy.astype(np.float64), x.shape, p, q, "dw4", pad, x=x, weight=w, need_dw=True)
+    sdx, sdw = oracle.condition_backward(dy, x.shape, p, q, "dw4", pad, x=x, weight=w, need_dw=True)
+    assert (np.abs(dx_only - rdx) <= UNIT[dtype] * np.abs(rdx) + UNIT_ABS[dtype] + 1e-5 * sdx + 1e-30).all()
+    assert (np.abs(dw_only - rdw) <= 1e-5 * sdw + 1e-30).all()
+
+
 def bicubic_init(p, q, C, noise_seed):
     """4x4 learned taps initialised to the bicubic outer product plus noise of
     variance 0.01, for every channel."""
