@@ -172,11 +172,17 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
       for (int k = 0; k < kDxPlanes; ++k) {
         const TS* dyrow = dyp + (k < np ? k : 0) * oplane + (int64_t)kh * a.Wo;
         const float* v = vv[k];
+        // Entries e >= nw (offsets 0: in bounds) enter with weight and sample
+        // both selected to 0, rather than behind a branch, so the weight reads
+        // of all entries are in flight together. (Adding +0 changes a sum only
+        // in the sign of a zero.)
         if constexpr (LEARNED) {
           const float* wr = smem + k * nwt + jh * TW.p * 16 + th * 4;
 #pragma unroll
-          for (int e = 0; e < kFastEntries; ++e)
-            if (e < nw) acc[k] = __builtin_fmaf(wr[wo[e]], v[e], acc[k]);
+          for (int e = 0; e < kFastEntries; ++e) {
+            const bool live = e < nw;
+            acc[k] = __builtin_fmaf(live ? wr[wo[e]] : 0.f, live ? v[e] : 0.f, acc[k]);
+          }
           for (int e = kFastEntries; e < nw; ++e) {
             const int we = rw[(3 + e) * fw];
             acc[k] = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc[k]);
@@ -184,8 +190,10 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
         } else {
           float inner = 0.f;
 #pragma unroll
-          for (int e = 0; e < kFastEntries; ++e)
-            if (e < nw) inner = __builtin_fmaf(ww[e], v[e], inner);
+          for (int e = 0; e < kFastEntries; ++e) {
+            const bool live = e < nw;
+            inner = __builtin_fmaf(live ? ww[e] : 0.f, live ? v[e] : 0.f, inner);
+          }
           for (int e = kFastEntries; e < nw; ++e) {
             const int we = rw[(3 + e) * fw];
             inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
