@@ -168,14 +168,16 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
 #pragma unroll
         for (int e = 0; e < kFastEntries; ++e) vv[k][e] = S::load(dyrow + kw[e]);
       }
+      // Entries e >= nw (offsets 0: in bounds) enter with weight and sample
+      // both selected to 0, rather than behind a branch, so the weight reads
+      // of all entries are in flight together. (Adding +0 changes a sum only
+      // in the sign of a zero.) The entries past the registers (columns at
+      // the padded edges) follow for every plane, after all planes' register
+      // entries: each plane's sum keeps its order.
+      float inner[kDxPlanes];
 #pragma unroll
       for (int k = 0; k < kDxPlanes; ++k) {
-        const TS* dyrow = dyp + (k < np ? k : 0) * oplane + (int64_t)kh * a.Wo;
         const float* v = vv[k];
-        // Entries e >= nw (offsets 0: in bounds) enter with weight and sample
-        // both selected to 0, rather than behind a branch, so the weight reads
-        // of all entries are in flight together. (Adding +0 changes a sum only
-        // in the sign of a zero.)
         if constexpr (LEARNED) {
           const float* wr = smem + k * nwt + jh * TW.p * 16 + th * 4;
 #pragma unroll
@@ -183,23 +185,33 @@ __global__ __launch_bounds__(kThreads) void dx_kernel(const BwdArgs a) {
             const bool live = e < nw;
             acc[k] = __builtin_fmaf(live ? wr[wo[e]] : 0.f, live ? v[e] : 0.f, acc[k]);
           }
-          for (int e = kFastEntries; e < nw; ++e) {
-            const int we = rw[(3 + e) * fw];
-            acc[k] = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc[k]);
-          }
         } else {
-          float inner = 0.f;
+          inner[k] = 0.f;
 #pragma unroll
           for (int e = 0; e < kFastEntries; ++e) {
             const bool live = e < nw;
-            inner = __builtin_fmaf(live ? ww[e] : 0.f, live ? v[e] : 0.f, inner);
+            inner[k] = __builtin_fmaf(live ? ww[e] : 0.f, live ? v[e] : 0.f, inner[k]);
           }
+        }
+      }
+      if (nw > kFastEntries) {
+#pragma unroll
+        for (int k = 0; k < kDxPlanes; ++k) {
+          const TS* dyrow = dyp + (k < np ? k : 0) * oplane + (int64_t)kh * a.Wo;
           for (int e = kFastEntries; e < nw; ++e) {
             const int we = rw[(3 + e) * fw];
-            inner = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner);
+            if constexpr (LEARNED) {
+              const float* wr = smem + k * nwt + jh * TW.p * 16 + th * 4;
+              acc[k] = __builtin_fmaf(wr[((we >> 2) & 31) * 16 + (we & 3)], S::load(dyrow + (we >> 7)), acc[k]);
+            } else {
+              inner[k] = __builtin_fmaf(TW.w[(we >> 2) & 31][we & 3], S::load(dyrow + (we >> 7)), inner[k]);
+            }
           }
-          acc[k] = __builtin_fmaf(TH.w[jh][th], inner, acc[k]);
         }
+      }
+      if constexpr (!LEARNED) {
+#pragma unroll
+        for (int k = 0; k < kDxPlanes; ++k) acc[k] = __builtin_fmaf(TH.w[jh][th], inner[k], acc[k]);
       }
     }
 #pragma unroll
